@@ -43,7 +43,9 @@
  *       not emptying.
  *   R11 rho_bar, u_bar: arithmetic mean over V in direction order.
  *   R12 EQ+NEQ uses the neighbour's own equilibrium; c^n = argmax_{i in V}
- *       c_i . n with the lowest index on ties; n from the fill level after S1.
+ *       c_i . n with the lowest index on ties (scores within 1e-12 |n|_1 of
+ *       the maximum tie, so rounding noise cannot decide); n from the fill
+ *       level after S1.
  *   R13 GEQ prefactor w rho tau / (2 c_s^2) (the printed 1/nu is read as tau).
  *   R14 EXT order drops to what the run of valid cells along c^n allows.
  *   R16 excess mass is split evenly over the D3Q19 neighbours that are
@@ -389,12 +391,17 @@ static void refill_cell(const orc_params *p, const uint8_t *flag, const uint8_t 
     if ((scheme == 1 || scheme == 3) && nv > 0) {
         double nrm[3];
         orc_normal(p, phi, x, nrm);
-        double best = -INFINITY;
+        /* c^n: largest c_i . n over valid directions; scores within a rounding
+         * tolerance of the maximum count as tied and the lowest index wins */
+        double best = -INFINITY, sc[Q];
         for (int i = 1; i < Q; ++i) {
             if (!valid[i]) continue;
-            double s = CX[i] * nrm[0] + CY[i] * nrm[1] + CZ[i] * nrm[2];
-            if (s > best) { best = s; cn = i; }
+            sc[i] = CX[i] * nrm[0] + CY[i] * nrm[1] + CZ[i] * nrm[2];
+            if (sc[i] > best) best = sc[i];
         }
+        double tol = 1e-12 * (fabs(nrm[0]) + fabs(nrm[1]) + fabs(nrm[2]));
+        for (int i = 1; i < Q && cn < 0; ++i)
+            if (valid[i] && sc[i] >= best - tol) cn = i;
     }
     if (scheme == 1 && cn > 0) { /* EQ+NEQ (R12) */
         double eqn[Q];
