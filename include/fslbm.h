@@ -1,0 +1,194 @@
+/*
+ * fslbm.h -- C ABI of the MI355X free-surface lattice Boltzmann (FSLBM) library.
+ *
+ * One call of fslbm_step advances B independent domains by whole FSLBM time
+ * steps of Schwarzmeier & Ruede, "Comparison of refilling schemes in the
+ * free-surface lattice Boltzmann method" (arXiv 2207.14496):
+ *   (a) D3Q19 stream-collide (Sec. 2.1, collision/streaming equations, Guo
+ *       forcing) with the anti-bounce-back free-surface condition at interface
+ *       cells (Sec. 2.2, boundary-condition equation) and half-way bounce-back
+ *       at walls (Sec. 2.1);
+ *   (b) interface mass exchange and fill-level update (Sec. 2.2, mass and
+ *       mass-flux equations; Sec. 3.2, mass-change equation);
+ *   (c) curvature from Parker-Youngs fill-level normals and the Laplace gas
+ *       pressure (Sec. 2.2, gas/volume/Laplace pressure equations);
+ *   (d) cell conversion with one of the five refilling schemes EQ, EQ+NEQ,
+ *       GEQ, EXT, AVG (Sec. 2.2 conversion rules; Sec. 3.1);
+ *   (e) excess-mass redistribution (Sec. 2.2, excess-mass equation).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Cells: domain b in [0,B), cell n = (z*ny + y)*nx + x in [0,N), N = nx*ny*nz.
+ *   Walls (no-slip, half-way bounce-back) lie half a cell outside the box on
+ *   every axis that is not periodic.
+ * - Canonical fields (what init accepts and read_fields returns), all in
+ *   DEVICE memory, C-contiguous:
+ *     flags  uint8   [B][N]      FSLBM_LIQUID / FSLBM_INTERFACE / FSLBM_GAS
+ *     pdf    double  [B][19][N]  post-collision PDFs f*_i of the last step
+ *                                 (unshifted; gas cells read back as 0)
+ *     mass   double  [B][N]      interface-cell mass m (Sec. 2.2); 0 elsewhere
+ *     phi    double  [B][N]      fill level (liquid 1, gas 0)
+ *     rho    double  [B][N]      sum_i f*_i (fluid cells; 0 in gas)
+ *     vel    double  [B][3][N]   sum_i c_i f*_i / rho - g/2 (fluid cells)
+ *   D3Q19 order: 0 rest; 1..6 = +x,-x,+y,-y,+z,-z; 7..18 = (1,1,0) (-1,-1,0)
+ *   (1,-1,0) (-1,1,0) (1,0,1) (-1,0,-1) (1,0,-1) (-1,0,1) (0,1,1) (0,-1,-1)
+ *   (0,1,-1) (0,-1,1); the opposite of i >= 1 is i+1 (odd i) or i-1 (even i).
+ * - Memory: the caller owns every byte.  The library never allocates device
+ *   memory; it carves the caller's workspace (fslbm_workspace_bytes) and keeps
+ *   only a small host-side context.  Inputs are read, never retained.
+ * - Streams: all device work is enqueued on params.stream (a hipStream_t;
+ *   NULL = the null stream).  fslbm_init, fslbm_read_fields and
+ *   fslbm_diagnostics synchronise that stream before returning; fslbm_step
+ *   does not.
+ * - Errors: every call returns an fslbm_status.  After a failure the context
+ *   is poisoned (every later call returns the same status) and
+ *   fslbm_last_error() describes the first failure.  No C++ exception crosses
+ *   this boundary.
+ */
+#ifndef FSLBM_H
+#define FSLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FSLBM_OK = 0,
+    FSLBM_EINVAL = -1,     /* invalid argument or initial state */
+    FSLBM_ENOMEM = -2,     /* workspace too small / host allocation failed */
+    FSLBM_EDEVICE = -3,    /* a HIP runtime call failed */
+    FSLBM_EUNSTABLE = -4,  /* non-finite values or |u| > c_s found by diagnostics */
+    FSLBM_ESTATE = -5      /* context poisoned by an earlier error */
+} fslbm_status;
+
+/* Refilling schemes of newly created interface cells (Sec. 3.1). */
+typedef enum {
+    FSLBM_REFILL_EQ = 0,      /* f_eq of the mean neighbour rho, u            */
+    FSLBM_REFILL_EQ_NEQ = 1,  /* EQ + non-equilibrium part of the neighbour   */
+                              /* best aligned with the interface normal       */
+    FSLBM_REFILL_GEQ = 2,     /* EQ + Grad's approximation of f_neq           */
+    FSLBM_REFILL_EXT = 3,     /* 2nd-order extrapolation along that direction */
+    FSLBM_REFILL_AVG = 4      /* mean of the neighbours' PDFs                 */
+} fslbm_refill;
+
+/* How PDFs are stored in HBM.  All modes store shifted populations
+ * s (f_i - w_i); F64 computes in double, the others in float.  Mass, fill level,
+ * excess mass and the conversion thresholds are double in every mode. */
+typedef enum {
+    FSLBM_F64 = 0,
+    FSLBM_F32 = 1,
+    FSLBM_F16 = 2,   /* s = 2^10 keeps |f - w| away from the fp16 subnormal range */
+    FSLBM_BF16 = 3
+} fslbm_storage;
+
+typedef enum { FSLBM_SRT = 0, FSLBM_TRT = 1 } fslbm_collision;
+
+enum { FSLBM_LIQUID = 1, FSLBM_INTERFACE = 2, FSLBM_GAS = 4 };
+
+/* Field bits of fslbm_read_fields. */
+enum {
+    FSLBM_FIELD_FLAGS = 1u << 0,
+    FSLBM_FIELD_PDF = 1u << 1,
+    FSLBM_FIELD_MASS = 1u << 2,
+    FSLBM_FIELD_PHI = 1u << 3,
+    FSLBM_FIELD_RHO = 1u << 4,
+    FSLBM_FIELD_VEL = 1u << 5
+};
+
+typedef struct fslbm_params {
+    int32_t nx, ny, nz;     /* cells per domain, each >= 1                          */
+    int32_t batch;          /* B >= 1 independent domains of the same size          */
+    int32_t periodic[3];    /* per axis: 1 periodic, 0 walls at both ends          */
+    int32_t collision;      /* fslbm_collision                                      */
+    int32_t storage;        /* fslbm_storage                                        */
+    int32_t refill;         /* fslbm_refill                                         */
+    double omega;           /* relaxation rate, in (0, 2) (omega+ for TRT)          */
+    double trt_lambda;      /* TRT magic parameter (3/16 puts walls half-way)       */
+    double gravity[3];      /* acceleration g, lattice units                        */
+    double sigma;           /* surface tension (0 disables curvature)               */
+    double p_volume;        /* constant gas (volume) pressure p_V, e.g. 1/3         */
+    double eps_phi;         /* conversion threshold, e.g. 1e-2                      */
+    const double *omega_b;  /* optional HOST array [B]: per-domain omega, or NULL   */
+    const double *gravity_b;/* optional HOST array [B][3]: per-domain g, or NULL    */
+    void *stream;           /* hipStream_t for all work                             */
+} fslbm_params;
+
+typedef struct fslbm_ctx fslbm_ctx;
+
+/* Per-domain diagnostics (fslbm_diagnostics). */
+typedef struct fslbm_diag {
+    double total_mass;      /* sum of liquid rho + interface m + reservoir (Sec. 3.2) */
+    double reservoir;       /* excess mass that found no interface receiver       */
+    double max_speed;       /* max |u| over fluid cells                           */
+    int64_t n_liquid, n_interface, n_gas;
+    int32_t finite;         /* 1 if every fluid PDF, m and phi is finite          */
+    int32_t pad;
+} fslbm_diag;
+
+/* Bytes of device workspace fslbm_init needs for these parameters.
+ * Returns FSLBM_EINVAL for invalid parameters. */
+fslbm_status fslbm_workspace_bytes(const fslbm_params *params, size_t *bytes);
+
+/*
+ * Create a context on the caller's workspace and load the initial state.
+ *   workspace  device buffer of at least fslbm_workspace_bytes, 256-byte aligned;
+ *              owned by the caller, borrowed until fslbm_destroy.
+ *   flags, phi canonical device arrays (required).
+ *   pdf        canonical f* [B][19][N] (device), or NULL: then f* = f_eq(rho, u)
+ *              (Sec. 2.1 equilibrium) from rho [B][N] and u [B][3][N] (device,
+ *              required in that case).
+ *   mass       interface mass [B][N] (device) or NULL: then m = phi * rho on
+ *              interface cells, with rho the given density when pdf is NULL
+ *              and sum_i f*_i otherwise (Sec. 2.2, mass definition).
+ * Rejects (FSLBM_EINVAL) omega outside (0,2), non-positive sizes, unknown enums,
+ * flags other than the three cell types, liquid phi != 1 or gas phi != 0, and a
+ * liquid cell with a gas D3Q19 neighbour (an open interface layer, Sec. 2.2).
+ * On success *out receives the context; on failure *out is NULL.
+ */
+fslbm_status fslbm_init(const fslbm_params *params, void *workspace, size_t bytes,
+                        const uint8_t *flags, const double *phi, const double *rho,
+                        const double *u, const double *pdf, const double *mass,
+                        fslbm_ctx **out);
+
+/* Enqueue nsteps >= 0 FSLBM time steps (a)-(e) on the context's stream.
+ * Asynchronous: device-side failures surface at the next synchronising call. */
+fslbm_status fslbm_step(fslbm_ctx *ctx, int32_t nsteps);
+
+/* Select the refilling scheme (fslbm_refill) used by subsequent steps. */
+fslbm_status fslbm_refill_scheme(fslbm_ctx *ctx, int32_t scheme);
+
+/* Enable (1) or disable (0) replaying the step sequence as a captured HIP
+ * graph (default: enabled).  Results are identical either way. */
+fslbm_status fslbm_use_graphs(fslbm_ctx *ctx, int32_t enable);
+
+/* Change the stream used by later calls (hipStream_t). */
+fslbm_status fslbm_set_stream(fslbm_ctx *ctx, void *stream);
+
+/*
+ * Copy the canonical state into caller device buffers.  dst[k] is the
+ * destination of field bit k (FSLBM_FIELD_*) and is only read when that bit is
+ * set in field_mask; layouts as in the header comment.  Synchronises.
+ * The reservoir scalar is returned by fslbm_diagnostics.
+ */
+fslbm_status fslbm_read_fields(fslbm_ctx *ctx, uint32_t field_mask, void *const *dst);
+
+/* Per-domain diagnostics into the HOST array out[B].  Synchronises.  Returns
+ * FSLBM_EUNSTABLE (without poisoning the context) if some domain holds
+ * non-finite values or a speed above c_s = 1/sqrt(3) (the stability criterion
+ * of Sec. 4). */
+fslbm_status fslbm_diagnostics(fslbm_ctx *ctx, fslbm_diag *out);
+
+/* Text of the first error seen by this context (or by the last failed init
+ * when ctx is NULL).  Never NULL. */
+const char *fslbm_last_error(const fslbm_ctx *ctx);
+
+/* Release the host-side context.  Does not touch the caller's workspace. */
+void fslbm_destroy(fslbm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FSLBM_H */

@@ -1,0 +1,638 @@
+// api.hip -- host side of the FSLBM library: workspace carving, the context,
+// initial-state upload, canonical read-back, diagnostics, HIP-graph replay of
+// the step sequence and the C ABI declared in include/fslbm.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/fslbm.h"
+#include "fslbm_kernels.hpp"
+#include "fslbm_math.hpp"
+
+using namespace fslbm;
+
+namespace {
+
+constexpr int DIAG_BLOCKS = 256;
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+size_t storage_bytes(int st) { return st == FSLBM_F64 ? 8 : (st == FSLBM_F32 ? 4 : 2); }
+
+// Byte offsets of every array inside the caller's workspace.
+struct Layout {
+    size_t pdf, flags, m, phi, uif, mex, rhoG, normal, band;
+    size_t lists[7];   // if0, if1, newg, froml, conv0, conv1, band
+    size_t cnt, nif, res, omega, grav, diag_d, diag_i;
+    size_t total;
+};
+
+bool make_layout(const fslbm_params &p, Layout &L) {
+    long long N = (long long)p.nx * p.ny * p.nz;
+    long long BN = N * p.batch;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
+    L.pdf = take(size_t(BN) * Q * storage_bytes(p.storage));
+    L.flags = take(size_t(BN) + 4);
+    L.m = take(size_t(BN) * 8);
+    L.phi = take(size_t(BN) * 8);
+    L.uif = take(size_t(BN) * 24);
+    L.mex = take(size_t(BN) * 8);
+    bool surf = p.sigma != 0.0;
+    L.rhoG = surf ? take(size_t(BN) * 8) : 0;
+    L.normal = surf ? take(size_t(BN) * 24) : 0;
+    L.band = surf ? take(size_t((BN + 31) / 32) * 4) : 0;
+    for (int k = 0; k < 7; ++k) L.lists[k] = (k == 6 && !surf) ? 0 : take(size_t(BN) * 4);
+    L.cnt = take(C_COUNT * 4);
+    L.nif = take(size_t(2 * p.batch) * 4);
+    L.res = take(size_t(2 * p.batch) * 8);
+    L.omega = take(size_t(p.batch) * 8);
+    L.grav = take(size_t(p.batch) * 24);
+    L.diag_d = take(size_t(p.batch) * DIAG_BLOCKS * 2 * 8);
+    L.diag_i = take(size_t(p.batch) * DIAG_BLOCKS * 4 * 8);
+    L.total = off;
+    return true;
+}
+
+const char *validate(const fslbm_params *p) {
+    if (!p) return "params is NULL";
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1 || p->batch < 1) return "sizes must be >= 1";
+    long long BN = (long long)p->nx * p->ny * p->nz * p->batch;
+    if (BN >= (1LL << 31) - 64) return "more than 2^31 cells in total";
+    if (!(p->omega > 0.0 && p->omega < 2.0)) return "omega must lie in (0, 2)";
+    if (p->collision != FSLBM_SRT && p->collision != FSLBM_TRT) return "unknown collision";
+    if (p->storage < FSLBM_F64 || p->storage > FSLBM_BF16) return "unknown storage";
+    if (p->refill < FSLBM_REFILL_EQ || p->refill > FSLBM_REFILL_AVG) return "unknown refill scheme";
+    if (p->collision == FSLBM_TRT && !(p->trt_lambda > 0.0)) return "trt_lambda must be > 0";
+    if (!(p->eps_phi >= 0.0)) return "eps_phi must be >= 0";
+    if (p->omega_b)
+        for (int b = 0; b < p->batch; ++b)
+            if (!(p->omega_b[b] > 0.0 && p->omega_b[b] < 2.0)) return "omega_b must lie in (0, 2)";
+    for (int a = 0; a < 3; ++a)
+        if (p->periodic[a] != 0 && p->periodic[a] != 1) return "periodic must be 0 or 1";
+    return nullptr;
+}
+
+std::string g_init_error = "no error";
+
+// ------------------------------------------------------------------ init kernels
+
+struct InitArgs {
+    StepArgs s;
+    const uint8_t *flags_in;
+    const double *phi_in, *rho_in, *u_in, *pdf_in, *mass_in;
+};
+
+template <int ST>
+__global__ void k_init_cells(InitArgs ia) {
+    const StepArgs &a = ia.s;
+    long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= a.g.BN) return;
+    using C = Codec<ST>;
+    typename C::M *pdf = static_cast<typename C::M *>(a.pdf);
+    Cell c = decode(a.g, gid);
+    const long long N = a.g.N;
+    uint8_t fl = ia.flags_in[gid];
+    double ph = ia.phi_in[gid];
+    int err = 0;
+    if (fl != F_LIQ && fl != F_IF && fl != F_GAS) { err |= E_BAD_FLAG; fl = F_GAS; }
+    if ((fl == F_LIQ && ph != 1.0) || (fl == F_GAS && ph != 0.0) || !isfinite(ph)) err |= E_BAD_PHI;
+    if (fl == F_LIQ) {
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            long long q = nb_dir(a.g, c, i);
+            if (q >= 0 && ia.flags_in[q] == F_GAS) err |= E_OPEN_LAYER;
+        }
+    }
+    if (err) atomicOr(a.cnt + C_ERR, err);
+    a.flags[gid] = fl;
+    a.phi[gid] = ph;
+    bool fluid = fl != F_GAS;
+    double d[Q];
+    if (!fluid) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) d[i] = 0.0;
+    } else if (ia.pdf_in) {
+        const double *src = ia.pdf_in + (long long)c.b * Q * N + c.n;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) d[i] = src[i * N] - wgt<double>(i);
+    } else {
+        double r = ia.rho_in[gid];
+        const double *u = ia.u_in + (long long)c.b * 3 * N + c.n;
+        double ux = u[0], uy = u[N], uz = u[2 * N];
+        double uu = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) d[i] = feq_shift<double>(i, r, r - 1.0, ux, uy, uz, uu);
+    }
+    // layout A: f*_i(x) in slot (opp(i), x)
+    typename C::M *base = pdf + (long long)c.b * Q * N + c.n;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) C::store(base + opp(i) * N, typename C::T(d[i]));
+    double m = 0.0;
+    if (fl == F_IF) {
+        if (ia.mass_in) {
+            m = ia.mass_in[gid];
+        } else {
+            double r;
+            if (ia.pdf_in) {
+                double s = 0.0;
+                const double *src = ia.pdf_in + (long long)c.b * Q * N + c.n;
+#pragma unroll
+                for (int i = 0; i < Q; ++i) s += src[i * N];
+                r = s;
+            } else {
+                r = ia.rho_in[gid];
+            }
+            m = ph * r;
+        }
+    }
+    a.m[gid] = m;
+}
+
+// Forced filling/emptying classes and the first interface list.
+__global__ void k_init_lists(StepArgs a) {
+    long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    bool in = gid < a.g.BN;
+    bool is_if = in && a.flags[gid] == F_IF;
+    if (is_if) {
+        Cell c = decode(a.g, gid);
+        bool has_liq = false, has_gas = false;
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            long long q = nb_dir(a.g, c, i);
+            if (q < 0) continue;
+            uint8_t fq = a.flags[q] & F_TYPE;
+            has_liq |= fq == F_LIQ;
+            has_gas |= fq == F_GAS;
+        }
+        a.flags[gid] = uint8_t(F_IF | (!has_liq ? F_NOFLUID : (!has_gas ? F_NOEMPTY : 0)));
+        atomicAdd(a.nif_dom + a.B + int(gid / a.g.N), 1);
+    }
+    wave_append(is_if, int32_t(gid), a.list_old, a.cnt + C_IF0, a.cap, a.cnt + C_ERR);
+}
+
+// ------------------------------------------------------------------ read-back
+
+struct ReadArgs {
+    StepArgs s;
+    int layoutB;
+    uint32_t mask;
+    uint8_t *flags;
+    double *pdf, *mass, *phi, *rho, *vel;
+};
+
+template <int ST>
+__global__ void k_read(ReadArgs r) {
+    const StepArgs &a = r.s;
+    long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= a.g.BN) return;
+    Cell c = decode(a.g, gid);
+    const long long N = a.g.N;
+    uint8_t fl = a.flags[gid] & F_TYPE;
+    bool fluid = fl != F_GAS;
+    if (r.mask & FSLBM_FIELD_FLAGS) r.flags[gid] = fl;
+    if (r.mask & FSLBM_FIELD_MASS) r.mass[gid] = fl == F_IF ? a.m[gid] : 0.0;
+    if (r.mask & FSLBM_FIELD_PHI) r.phi[gid] = a.phi[gid];
+    if (r.mask & (FSLBM_FIELD_PDF | FSLBM_FIELD_RHO | FSLBM_FIELD_VEL)) {
+        double d[Q];
+        if (fluid) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                Slot s = slot_of(a.g, r.layoutB, c, gid, i);
+                using Cd = Codec<ST>;
+                d[i] = double(Cd::load(static_cast<const typename Cd::M *>(a.pdf) + slot_index(a.g, s)));
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) d[i] = 0.0;
+        }
+        if (r.mask & FSLBM_FIELD_PDF) {
+            double *dst = r.pdf + (long long)c.b * Q * N + c.n;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) dst[i * N] = fluid ? wgt<double>(i) + d[i] : 0.0;
+        }
+        if (r.mask & (FSLBM_FIELD_RHO | FSLBM_FIELD_VEL)) {
+            double rho = 0.0, ux = 0.0, uy = 0.0, uz = 0.0;
+            if (fluid) {
+                const double *gr = a.grav + 3 * c.b;
+                moments_post(d, gr[0], gr[1], gr[2], rho, ux, uy, uz);
+            }
+            if (r.mask & FSLBM_FIELD_RHO) r.rho[gid] = rho;
+            if (r.mask & FSLBM_FIELD_VEL) {
+                double *v = r.vel + (long long)c.b * 3 * N + c.n;
+                v[0] = ux; v[N] = uy; v[2 * N] = uz;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ diagnostics
+
+// Per-domain partial sums with a fixed-order tree (deterministic).
+template <int ST>
+__global__ __launch_bounds__(256) void k_diag_partial(StepArgs a, int layoutB, double *pd,
+                                                      long long *pi) {
+    const int b = blockIdx.y;
+    const long long N = a.g.N;
+    double mass = 0.0, vmax = 0.0;
+    long long nl = 0, ni = 0, ng = 0, bad = 0;
+    for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < N;
+         n += (long long)gridDim.x * blockDim.x) {
+        long long gid = (long long)b * N + n;
+        uint8_t fl = a.flags[gid] & F_TYPE;
+        if (fl == F_GAS) { ++ng; continue; }
+        double d[Q];
+        Cell c = decode(a.g, gid);
+        bool fin = true;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            Slot s = slot_of(a.g, layoutB, c, gid, i);
+            using Cd = Codec<ST>;
+            d[i] = double(Cd::load(static_cast<const typename Cd::M *>(a.pdf) + slot_index(a.g, s)));
+            fin &= isfinite(d[i]);
+        }
+        const double *gr = a.grav + 3 * b;
+        double rho, ux, uy, uz;
+        moments_post(d, gr[0], gr[1], gr[2], rho, ux, uy, uz);
+        double sp = sqrt(ux * ux + uy * uy + uz * uz);
+        if (fl == F_LIQ) { ++nl; mass += rho; }
+        else { ++ni; mass += a.m[gid]; fin &= isfinite(a.m[gid]) && isfinite(a.phi[gid]); }
+        vmax = fin ? (sp > vmax ? sp : vmax) : vmax;
+        bad += !fin || !isfinite(sp);
+    }
+    __shared__ double sm[256], sv[256];
+    __shared__ long long s0[256], s1[256], s2[256], s3[256];
+    int t = threadIdx.x;
+    sm[t] = mass; sv[t] = vmax; s0[t] = nl; s1[t] = ni; s2[t] = ng; s3[t] = bad;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) {
+            sm[t] += sm[t + w];
+            sv[t] = sv[t] > sv[t + w] ? sv[t] : sv[t + w];
+            s0[t] += s0[t + w]; s1[t] += s1[t + w]; s2[t] += s2[t + w]; s3[t] += s3[t + w];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        long long o = (long long)b * gridDim.x + blockIdx.x;
+        pd[2 * o] = sm[0];
+        pd[2 * o + 1] = sv[0];
+        pi[4 * o] = s0[0]; pi[4 * o + 1] = s1[0]; pi[4 * o + 2] = s2[0]; pi[4 * o + 3] = s3[0];
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ context
+
+struct fslbm_ctx {
+    fslbm_params p{};
+    Layout L{};
+    char *ws = nullptr;
+    std::vector<double> omega_h, grav_h;
+    long long t = 0;                 // steps done
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    bool graphs = true;
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    fslbm_status status = FSLBM_OK;
+    std::string err = "no error";
+};
+
+namespace {
+
+template <typename T>
+T *at(fslbm_ctx *c, size_t off) { return reinterpret_cast<T *>(c->ws + off); }
+
+StepArgs make_args(fslbm_ctx *c, int parity) {
+    StepArgs a{};
+    const fslbm_params &p = c->p;
+    a.g.nx = p.nx; a.g.ny = p.ny; a.g.nz = p.nz;
+    for (int k = 0; k < 3; ++k) a.g.per[k] = p.periodic[k];
+    a.g.N = (long long)p.nx * p.ny * p.nz;
+    a.g.BN = a.g.N * p.batch;
+    a.pdf = c->ws + c->L.pdf;
+    a.flags = at<uint8_t>(c, c->L.flags);
+    a.m = at<double>(c, c->L.m);
+    a.phi = at<double>(c, c->L.phi);
+    a.uif = at<double>(c, c->L.uif);
+    a.mex = at<double>(c, c->L.mex);
+    bool surf = p.sigma != 0.0;
+    a.rhoG = surf ? at<double>(c, c->L.rhoG) : nullptr;
+    a.normal = surf ? at<double>(c, c->L.normal) : nullptr;
+    a.band = surf ? at<uint32_t>(c, c->L.band) : nullptr;
+    a.omega = at<double>(c, c->L.omega);
+    a.grav = at<double>(c, c->L.grav);
+    a.trt_lambda = p.trt_lambda;
+    a.sigma = p.sigma;
+    a.p_volume = p.p_volume;
+    a.eps_phi = p.eps_phi;
+    int32_t *lists[7];
+    for (int k = 0; k < 7; ++k) lists[k] = c->L.lists[k] ? at<int32_t>(c, c->L.lists[k]) : nullptr;
+    a.list_old = lists[parity];
+    a.list_new = lists[1 - parity];
+    a.list_newg = lists[2];
+    a.list_froml = lists[3];
+    a.list_conv = lists[4 + parity];
+    a.list_conv_prev = lists[4 + (1 - parity)];
+    a.list_band = lists[6];
+    a.cnt = at<int32_t>(c, c->L.cnt);
+    a.nif_dom = at<int32_t>(c, c->L.nif);
+    a.res = at<double>(c, c->L.res);
+    a.parity = parity;
+    a.B = p.batch;
+    a.cap = a.g.BN;
+    return a;
+}
+
+fslbm_status fail(fslbm_ctx *c, fslbm_status s, const std::string &msg) {
+    if (c->status == FSLBM_OK) {
+        c->status = s;
+        c->err = msg;
+    }
+    return c->status;
+}
+
+bool hip_ok(fslbm_ctx *c, hipError_t e, const char *what) {
+    if (e == hipSuccess) return true;
+    fail(c, FSLBM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    return false;
+}
+
+// Check the sticky device error word (requires a synchronised stream).
+bool device_errors_ok(fslbm_ctx *c) {
+    int32_t cnt[C_COUNT];
+    if (!hip_ok(c, hipMemcpy(cnt, at<int32_t>(c, c->L.cnt), sizeof cnt, hipMemcpyDeviceToHost),
+                "hipMemcpy(counters)"))
+        return false;
+    int e = cnt[C_ERR];
+    if (e & E_LIST_OVERFLOW) { fail(c, FSLBM_EDEVICE, "internal list overflow"); return false; }
+    if (e & E_BAD_FLAG) { fail(c, FSLBM_EINVAL, "flags must be 1 (liquid), 2 (interface) or 4 (gas)"); return false; }
+    if (e & E_BAD_PHI) { fail(c, FSLBM_EINVAL, "liquid cells need phi = 1 and gas cells phi = 0 (finite)"); return false; }
+    if (e & E_OPEN_LAYER) { fail(c, FSLBM_EINVAL, "a liquid cell has a gas neighbour (open interface layer)"); return false; }
+    return true;
+}
+
+void drop_graphs(fslbm_ctx *c) {
+    for (int k = 0; k < 2; ++k)
+        if (c->exec[k]) { (void)hipGraphExecDestroy(c->exec[k]); c->exec[k] = nullptr; }
+}
+
+bool capture(fslbm_ctx *c, int parity) {
+    if (!c->cap_stream &&
+        !hip_ok(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "hipStreamCreate"))
+        return false;
+    hipGraph_t g = nullptr;
+    if (!hip_ok(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal),
+                "hipStreamBeginCapture"))
+        return false;
+    launch_step(make_args(c, parity), c->p.storage, c->p.collision, c->p.refill, c->cap_stream);
+    hipError_t le = hipGetLastError();
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    if (!hip_ok(c, le, "kernel launch (capture)") || !hip_ok(c, e, "hipStreamEndCapture")) return false;
+    hipError_t ie = hipGraphInstantiate(&c->exec[parity], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    return hip_ok(c, ie, "hipGraphInstantiate");
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+fslbm_status fslbm_workspace_bytes(const fslbm_params *params, size_t *bytes) {
+    const char *why = validate(params);
+    if (why || !bytes) { g_init_error = why ? why : "bytes is NULL"; return FSLBM_EINVAL; }
+    Layout L;
+    make_layout(*params, L);
+    *bytes = L.total;
+    return FSLBM_OK;
+}
+
+fslbm_status fslbm_init(const fslbm_params *params, void *workspace, size_t bytes,
+                        const uint8_t *flags, const double *phi, const double *rho,
+                        const double *u, const double *pdf, const double *mass,
+                        fslbm_ctx **out) {
+    if (out) *out = nullptr;
+    const char *why = validate(params);
+    if (!why && !out) why = "out is NULL";
+    if (!why && (!workspace || !flags || !phi)) why = "workspace, flags and phi are required";
+    if (!why && !pdf && (!rho || !u)) why = "rho and u are required when pdf is NULL";
+    if (!why && (reinterpret_cast<uintptr_t>(workspace) & 255)) why = "workspace must be 256-byte aligned";
+    if (why) { g_init_error = why; return FSLBM_EINVAL; }
+    fslbm_ctx *c = new (std::nothrow) fslbm_ctx;
+    if (!c) { g_init_error = "host allocation failed"; return FSLBM_ENOMEM; }
+    c->p = *params;
+    c->p.omega_b = nullptr;
+    c->p.gravity_b = nullptr;
+    make_layout(c->p, c->L);
+    if (bytes < c->L.total) {
+        g_init_error = "workspace too small";
+        delete c;
+        return FSLBM_ENOMEM;
+    }
+    c->ws = static_cast<char *>(workspace);
+    c->stream = static_cast<hipStream_t>(params->stream);
+    const int B = params->batch;
+    c->omega_h.resize(B);
+    c->grav_h.resize(3 * B);
+    for (int b = 0; b < B; ++b) {
+        c->omega_h[b] = params->omega_b ? params->omega_b[b] : params->omega;
+        for (int k = 0; k < 3; ++k)
+            c->grav_h[3 * b + k] = params->gravity_b ? params->gravity_b[3 * b + k] : params->gravity[k];
+    }
+    StepArgs a = make_args(c, 0);
+    bool ok = hip_ok(c, hipMemcpyAsync(at<double>(c, c->L.omega), c->omega_h.data(), 8 * B,
+                                       hipMemcpyHostToDevice, c->stream), "hipMemcpy(omega)") &&
+              hip_ok(c, hipMemcpyAsync(at<double>(c, c->L.grav), c->grav_h.data(), 24 * B,
+                                       hipMemcpyHostToDevice, c->stream), "hipMemcpy(gravity)") &&
+              hip_ok(c, hipMemsetAsync(a.cnt, 0, C_COUNT * 4, c->stream), "hipMemset") &&
+              hip_ok(c, hipMemsetAsync(a.nif_dom, 0, 8 * B, c->stream), "hipMemset") &&
+              hip_ok(c, hipMemsetAsync(a.res, 0, 16 * B, c->stream), "hipMemset") &&
+              hip_ok(c, hipMemsetAsync(a.mex, 0, size_t(a.g.BN) * 8, c->stream), "hipMemset") &&
+              hip_ok(c, hipMemsetAsync(a.uif, 0, size_t(a.g.BN) * 24, c->stream), "hipMemset");
+    if (ok && a.band)
+        ok = hip_ok(c, hipMemsetAsync(a.band, 0, size_t((a.g.BN + 31) / 32) * 4, c->stream), "hipMemset") &&
+             hip_ok(c, hipMemsetAsync(a.rhoG, 0, size_t(a.g.BN) * 8, c->stream), "hipMemset") &&
+             hip_ok(c, hipMemsetAsync(a.normal, 0, size_t(a.g.BN) * 24, c->stream), "hipMemset");
+    if (ok) {
+        // also clear the PDF array so gas slots hold finite values
+        ok = hip_ok(c, hipMemsetAsync(a.pdf, 0, size_t(a.g.BN) * Q * storage_bytes(c->p.storage), c->stream),
+                    "hipMemset(pdf)");
+    }
+    if (ok) {
+        InitArgs ia{a, flags, phi, rho, u, pdf, mass};
+        unsigned nblk = unsigned((a.g.BN + 255) / 256);
+        switch (c->p.storage) {
+            case FSLBM_F64: hipLaunchKernelGGL(k_init_cells<ST_F64>, dim3(nblk), dim3(256), 0, c->stream, ia); break;
+            case FSLBM_F32: hipLaunchKernelGGL(k_init_cells<ST_F32>, dim3(nblk), dim3(256), 0, c->stream, ia); break;
+            case FSLBM_F16: hipLaunchKernelGGL(k_init_cells<ST_F16>, dim3(nblk), dim3(256), 0, c->stream, ia); break;
+            default: hipLaunchKernelGGL(k_init_cells<ST_BF16>, dim3(nblk), dim3(256), 0, c->stream, ia); break;
+        }
+        ok = hip_ok(c, hipGetLastError(), "k_init_cells");
+        if (ok) {
+            hipLaunchKernelGGL(k_init_lists, dim3(nblk), dim3(256), 0, c->stream, a);
+            ok = hip_ok(c, hipGetLastError(), "k_init_lists");
+        }
+    }
+    ok = ok && hip_ok(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize") && device_errors_ok(c);
+    if (!ok) {
+        g_init_error = c->err;
+        fslbm_status s = c->status;
+        delete c;
+        return s;
+    }
+    *out = c;
+    return FSLBM_OK;
+}
+
+fslbm_status fslbm_step(fslbm_ctx *c, int32_t nsteps) {
+    if (!c) return FSLBM_EINVAL;
+    if (c->status != FSLBM_OK) return c->status;
+    if (nsteps < 0) return fail(c, FSLBM_EINVAL, "nsteps must be >= 0");
+    for (int32_t s = 0; s < nsteps; ++s) {
+        int parity = int(c->t & 1);
+        if (c->graphs) {
+            if (!c->exec[parity] && !capture(c, parity)) return c->status;
+            if (!hip_ok(c, hipGraphLaunch(c->exec[parity], c->stream), "hipGraphLaunch")) return c->status;
+        } else {
+            launch_step(make_args(c, parity), c->p.storage, c->p.collision, c->p.refill, c->stream);
+            if (!hip_ok(c, hipGetLastError(), "step kernel launch")) return c->status;
+        }
+        ++c->t;
+    }
+    return FSLBM_OK;
+}
+
+fslbm_status fslbm_refill_scheme(fslbm_ctx *c, int32_t scheme) {
+    if (!c) return FSLBM_EINVAL;
+    if (c->status != FSLBM_OK) return c->status;
+    if (scheme < FSLBM_REFILL_EQ || scheme > FSLBM_REFILL_AVG) return fail(c, FSLBM_EINVAL, "unknown refill scheme");
+    if (scheme != c->p.refill) {
+        c->p.refill = scheme;
+        drop_graphs(c);
+    }
+    return FSLBM_OK;
+}
+
+fslbm_status fslbm_use_graphs(fslbm_ctx *c, int32_t enable) {
+    if (!c) return FSLBM_EINVAL;
+    if (c->status != FSLBM_OK) return c->status;
+    c->graphs = enable != 0;
+    return FSLBM_OK;
+}
+
+fslbm_status fslbm_set_stream(fslbm_ctx *c, void *stream) {
+    if (!c) return FSLBM_EINVAL;
+    if (c->status != FSLBM_OK) return c->status;
+    c->stream = static_cast<hipStream_t>(stream);
+    return FSLBM_OK;
+}
+
+fslbm_status fslbm_read_fields(fslbm_ctx *c, uint32_t mask, void *const *dst) {
+    if (!c) return FSLBM_EINVAL;
+    if (c->status != FSLBM_OK) return c->status;
+    if (mask & ~0x3Fu) return fail(c, FSLBM_EINVAL, "unknown field bits");
+    if (!dst && mask) return fail(c, FSLBM_EINVAL, "dst is NULL");
+    for (int k = 0; k < 6; ++k)
+        if ((mask >> k & 1u) && !dst[k]) return fail(c, FSLBM_EINVAL, "NULL destination for a requested field");
+    ReadArgs r{};
+    r.s = make_args(c, int(c->t & 1));
+    r.layoutB = int(c->t & 1);
+    r.mask = mask;
+    if (mask) {
+        r.flags = static_cast<uint8_t *>(dst[0]);
+        r.pdf = static_cast<double *>(dst[1]);
+        r.mass = static_cast<double *>(dst[2]);
+        r.phi = static_cast<double *>(dst[3]);
+        r.rho = static_cast<double *>(dst[4]);
+        r.vel = static_cast<double *>(dst[5]);
+        unsigned nblk = unsigned((r.s.g.BN + 255) / 256);
+        switch (c->p.storage) {
+            case FSLBM_F64: hipLaunchKernelGGL(k_read<ST_F64>, dim3(nblk), dim3(256), 0, c->stream, r); break;
+            case FSLBM_F32: hipLaunchKernelGGL(k_read<ST_F32>, dim3(nblk), dim3(256), 0, c->stream, r); break;
+            case FSLBM_F16: hipLaunchKernelGGL(k_read<ST_F16>, dim3(nblk), dim3(256), 0, c->stream, r); break;
+            default: hipLaunchKernelGGL(k_read<ST_BF16>, dim3(nblk), dim3(256), 0, c->stream, r); break;
+        }
+        if (!hip_ok(c, hipGetLastError(), "k_read")) return c->status;
+    }
+    if (!hip_ok(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize")) return c->status;
+    if (!device_errors_ok(c)) return c->status;
+    return FSLBM_OK;
+}
+
+fslbm_status fslbm_diagnostics(fslbm_ctx *c, fslbm_diag *out) {
+    if (!c) return FSLBM_EINVAL;
+    if (c->status != FSLBM_OK) return c->status;
+    if (!out) return fail(c, FSLBM_EINVAL, "out is NULL");
+    const int B = c->p.batch;
+    StepArgs a = make_args(c, int(c->t & 1));
+    double *pd = at<double>(c, c->L.diag_d);
+    long long *pi = at<long long>(c, c->L.diag_i);
+    switch (c->p.storage) {
+        case FSLBM_F64: hipLaunchKernelGGL(k_diag_partial<ST_F64>, dim3(DIAG_BLOCKS, B), dim3(256), 0, c->stream, a, int(c->t & 1), pd, pi); break;
+        case FSLBM_F32: hipLaunchKernelGGL(k_diag_partial<ST_F32>, dim3(DIAG_BLOCKS, B), dim3(256), 0, c->stream, a, int(c->t & 1), pd, pi); break;
+        case FSLBM_F16: hipLaunchKernelGGL(k_diag_partial<ST_F16>, dim3(DIAG_BLOCKS, B), dim3(256), 0, c->stream, a, int(c->t & 1), pd, pi); break;
+        default: hipLaunchKernelGGL(k_diag_partial<ST_BF16>, dim3(DIAG_BLOCKS, B), dim3(256), 0, c->stream, a, int(c->t & 1), pd, pi); break;
+    }
+    if (!hip_ok(c, hipGetLastError(), "k_diag_partial")) return c->status;
+    std::vector<double> hd(size_t(B) * DIAG_BLOCKS * 2);
+    std::vector<long long> hi(size_t(B) * DIAG_BLOCKS * 4);
+    std::vector<double> res(2 * B);
+    std::vector<int32_t> nif(2 * B);
+    if (!hip_ok(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize") ||
+        !hip_ok(c, hipMemcpy(hd.data(), pd, hd.size() * 8, hipMemcpyDeviceToHost), "hipMemcpy") ||
+        !hip_ok(c, hipMemcpy(hi.data(), pi, hi.size() * 8, hipMemcpyDeviceToHost), "hipMemcpy") ||
+        !hip_ok(c, hipMemcpy(res.data(), a.res, 16 * B, hipMemcpyDeviceToHost), "hipMemcpy") ||
+        !hip_ok(c, hipMemcpy(nif.data(), a.nif_dom, 8 * B, hipMemcpyDeviceToHost), "hipMemcpy"))
+        return c->status;
+    if (!device_errors_ok(c)) return c->status;
+    bool unstable = false;
+    const double cs = 1.0 / std::sqrt(3.0);
+    for (int b = 0; b < B; ++b) {
+        fslbm_diag d{};
+        double mass = 0.0, vmax = 0.0;
+        long long cnt[4] = {0, 0, 0, 0};
+        for (int k = 0; k < DIAG_BLOCKS; ++k) {
+            size_t o = size_t(b) * DIAG_BLOCKS + k;
+            mass += hd[2 * o];
+            vmax = std::max(vmax, hd[2 * o + 1]);
+            for (int j = 0; j < 4; ++j) cnt[j] += hi[4 * o + j];
+        }
+        double r = 0.0;
+        if (c->t > 0) {
+            int p = int((c->t - 1) & 1);
+            r = nif[p * B + b] > 0 ? 0.0 : res[p * B + b];
+        }
+        d.reservoir = r;
+        d.total_mass = mass + r;
+        d.max_speed = vmax;
+        d.n_liquid = cnt[0];
+        d.n_interface = cnt[1];
+        d.n_gas = cnt[2];
+        d.finite = cnt[3] == 0;
+        unstable |= !d.finite || !(vmax <= cs);
+        out[b] = d;
+    }
+    return unstable ? FSLBM_EUNSTABLE : FSLBM_OK;
+}
+
+const char *fslbm_last_error(const fslbm_ctx *c) {
+    return c ? c->err.c_str() : g_init_error.c_str();
+}
+
+void fslbm_destroy(fslbm_ctx *c) {
+    if (!c) return;
+    drop_graphs(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    delete c;
+}
+
+}  // extern "C"

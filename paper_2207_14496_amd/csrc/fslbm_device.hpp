@@ -1,0 +1,214 @@
+// fslbm_device.hpp -- device-side building blocks of the FSLBM step for gfx950:
+// the D3Q19 lattice, PDF storage codecs, the in-place (AA) slot map, cell
+// geometry and the per-launch argument block shared by all kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fslbm {
+
+// ------------------------------------------------------------------ lattice
+// D3Q19 (Sec. 2.1): rest, 6 faces, 12 edges; opposite directions adjacent.
+constexpr int Q = 19;
+// All direction loops are fully unrolled, so these fold to constants.
+__host__ __device__ constexpr int cx(int i) {
+    constexpr int t[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+    return t[i];
+}
+__host__ __device__ constexpr int cy(int i) {
+    constexpr int t[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+    return t[i];
+}
+__host__ __device__ constexpr int cz(int i) {
+    constexpr int t[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+    return t[i];
+}
+__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+template <typename T>
+__host__ __device__ constexpr T wgt(int i) {
+    return i == 0 ? T(1) / T(3) : (i <= 6 ? T(1) / T(18) : T(1) / T(36));
+}
+
+// ------------------------------------------------------------------ flag bits
+// Low three bits are the canonical cell types.  The rest are internal:
+//   NOFLUID / NOEMPTY  forced emptying / filling classes of interface cells
+//   MARK_A  interface: fill level above 1+eps (to liquid); gas: new interface
+//   MARK_B  interface: fill level below -eps (to gas); liquid: becomes interface
+//   CONV    liquid or gas cell that was interface before this step's conversion
+enum : uint8_t {
+    F_LIQ = 1, F_IF = 2, F_GAS = 4, F_TYPE = 7,
+    F_NOFLUID = 8, F_NOEMPTY = 16,
+    F_MARK_A = 32, F_MARK_B = 64, F_CONV = 128
+};
+
+// ------------------------------------------------------------------ storage
+// PDFs are kept as shifted populations d_i = s (f_i - w_i).
+enum Storage { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_BF16 = 3 };
+
+template <int S> struct Codec;
+template <> struct Codec<ST_F64> {
+    using T = double;      // arithmetic type
+    using M = double;      // memory type
+    __device__ static T load(const M *p) { return *p; }
+    __device__ static void store(M *p, T v) { *p = v; }
+};
+template <> struct Codec<ST_F32> {
+    using T = float;
+    using M = float;
+    __device__ static T load(const M *p) { return *p; }
+    __device__ static void store(M *p, T v) { *p = v; }
+};
+template <> struct Codec<ST_F16> {
+    using T = float;
+    using M = _Float16;
+    static constexpr float S = 1024.0f, IS = 1.0f / 1024.0f;  // exact powers of two
+    __device__ static T load(const M *p) { return float(*p) * IS; }
+    __device__ static void store(M *p, T v) { *p = (_Float16)(v * S); }
+};
+template <> struct Codec<ST_BF16> {
+    using T = float;
+    using M = uint16_t;
+    __device__ static T load(const M *p) { return __uint_as_float(uint32_t(*p) << 16); }
+    __device__ static void store(M *p, T v) {
+        // round to nearest even on the upper 16 bits (finite inputs)
+        uint32_t u = __float_as_uint(v);
+        u += 0x7FFFu + ((u >> 16) & 1u);
+        *p = uint16_t(u >> 16);
+    }
+};
+
+// ------------------------------------------------------------------ geometry
+struct Geom {
+    int nx, ny, nz;
+    int per[3];
+    long long N;      // cells per domain
+    long long BN;     // cells in all domains
+};
+
+// Neighbour of cell (x,y,z) shifted by (dx,dy,dz) inside the same domain:
+// returns the cell index (domain-local) or -1 for a wall.
+__device__ __forceinline__ long long nb_local(const Geom &g, int x, int y, int z, int dx, int dy,
+                                              int dz) {
+    x += dx; y += dy; z += dz;
+    if (x < 0 || x >= g.nx) { if (!g.per[0]) return -1; x = x < 0 ? x + g.nx : x - g.nx; }
+    if (y < 0 || y >= g.ny) { if (!g.per[1]) return -1; y = y < 0 ? y + g.ny : y - g.ny; }
+    if (z < 0 || z >= g.nz) { if (!g.per[2]) return -1; z = z < 0 ? z + g.nz : z - g.nz; }
+    return ((long long)z * g.ny + y) * g.nx + x;
+}
+
+struct Cell {
+    int b, x, y, z;
+    long long n;   // domain-local index
+};
+
+__device__ __forceinline__ Cell decode(const Geom &g, long long gid) {
+    Cell c;
+    c.b = int(gid / g.N);
+    c.n = gid - (long long)c.b * g.N;
+    long long r = c.n / g.nx;
+    c.x = int(c.n - r * g.nx);
+    c.y = int(r % g.ny);
+    c.z = int(r / g.ny);
+    return c;
+}
+
+// Global index of the neighbour along c_i, or -1 for a wall.
+__device__ __forceinline__ long long nb_dir(const Geom &g, const Cell &c, int i) {
+    long long k = nb_local(g, c.x, c.y, c.z, cx(i), cy(i), cz(i));
+    return k < 0 ? -1 : (long long)c.b * g.N + k;
+}
+
+// ------------------------------------------------------------------ AA slots
+// In-place streaming (AA pattern, Bailey et al. 2009).  After an even number of
+// steps ("layout A") f*_i(x) sits in slot (opp(i), x).  After an odd number
+// ("layout B") it sits in slot (i, x + c_i), or in (opp(i), x) when x + c_i is
+// a wall.  Slot (d, cell) of domain b is pdf[(b*19 + d)*N + n].
+struct Slot {
+    int d;
+    long long cell;   // global cell index
+};
+__device__ __forceinline__ Slot slot_of(const Geom &g, int layoutB, const Cell &c, long long gid,
+                                        int i) {
+    if (!layoutB) return Slot{opp(i), gid};
+    long long k = nb_dir(g, c, i);
+    if (k < 0) return Slot{opp(i), gid};
+    return Slot{i, k};
+}
+__device__ __forceinline__ long long slot_index(const Geom &g, Slot s) {
+    long long b = s.cell / g.N;
+    return (b * Q + s.d) * g.N + (s.cell - b * g.N);
+}
+
+// ------------------------------------------------------------------ arguments
+struct StepArgs {
+    Geom g;
+    void *pdf;
+    uint8_t *flags;
+    double *m, *phi;
+    double *rhoG;          // [BN] gas density at interface cells (sigma != 0), else null
+    double *uif;           // [3][BN] interface velocity from f*(t) for anti-bounce-back
+    double *mex;           // [BN] excess mass share of converted cells
+    double *normal;        // [3][BN] unit normals on the band (sigma != 0)
+    uint32_t *band;        // [ceil(BN/32)] band membership bits (sigma != 0)
+    const double *omega;   // [B]
+    const double *grav;    // [B][3]
+    double trt_lambda;
+    double sigma, p_volume, eps_phi;
+    int32_t *list_old, *list_new;   // interface lists (this step / next step)
+    int32_t *list_newg, *list_froml, *list_conv, *list_conv_prev, *list_band;
+    int32_t *cnt;          // device counters, see Counter
+    int32_t *nif_dom;      // [2][B] interface cells per domain after conversion
+    double *res;           // [2][B] reservoir of excess mass
+    int parity;            // step parity: 0 = layout A -> B, 1 = layout B -> A
+    int B;
+    long long cap;         // capacity of every list
+};
+
+// Counter slots in StepArgs::cnt.  Index by parity where noted.
+enum Counter {
+    C_IF0 = 0, C_IF1 = 1,        // interface list sizes (list 0 / list 1)
+    C_NEWG = 2, C_FROML = 3,     // this step's conversion lists
+    C_CONV0 = 4, C_CONV1 = 5,    // converted interface cells (by step parity)
+    C_BAND = 6,
+    C_ERR = 7,                   // sticky device error bits
+    C_COUNT = 8
+};
+enum DeviceError { E_LIST_OVERFLOW = 1, E_OPEN_LAYER = 2, E_BAD_FLAG = 4, E_BAD_PHI = 8 };
+
+// Append `v` to list[*count] with one atomic per wavefront.
+__device__ __forceinline__ void wave_append(bool pred, int32_t v, int32_t *list, int32_t *count,
+                                            long long cap, int32_t *err) {
+    unsigned long long mask = __ballot(pred);
+    if (mask == 0) return;
+    int lane = __lane_id();
+    int leader = __ffsll((long long)mask) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(count, __popcll(mask));
+    base = __shfl(base, leader);
+    if (pred) {
+        unsigned long long below = mask & ((1ull << lane) - 1ull);
+        long long pos = (long long)base + __popcll(below);
+        if (pos < cap) list[pos] = v;
+        else atomicOr(err, E_LIST_OVERFLOW);
+    }
+}
+
+// Byte-granular atomic OR on the flag array (4-byte aligned, padded).
+// Returns the previous byte value.
+__device__ __forceinline__ uint8_t flag_or(uint8_t *flags, long long i, uint8_t bits) {
+    uintptr_t a = reinterpret_cast<uintptr_t>(flags + i);
+    unsigned int *w = reinterpret_cast<unsigned int *>(a & ~uintptr_t(3));
+    int sh = int(a & 3) * 8;
+    unsigned int old = atomicOr(w, (unsigned int)bits << sh);
+    return uint8_t(old >> sh);
+}
+// Byte-granular atomic clear of `bits`.
+__device__ __forceinline__ void flag_clear(uint8_t *flags, long long i, uint8_t bits) {
+    uintptr_t a = reinterpret_cast<uintptr_t>(flags + i);
+    unsigned int *w = reinterpret_cast<unsigned int *>(a & ~uintptr_t(3));
+    int sh = int(a & 3) * 8;
+    atomicAnd(w, ~((unsigned int)bits << sh));
+}
+
+}  // namespace fslbm

@@ -1,0 +1,147 @@
+"""GPU vs oracle parity through the C ABI (FP64 storage: flags bit-exact,
+PDFs / interface mass / fill level within 1e-12)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from _gpu import announce, compare, fields_np, params_from_oracle, sim_from_states
+from _util import oracle_params, oracle_state
+from paper_2207_14496_amd import fslbm, setups
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _run_pair(setup_or_p, st0, nsteps, what, tol=1e-12, **kw):
+    p = setup_or_p
+    sim = sim_from_states(p, [st0], **kw)
+    ref = st0.copy()
+    for k in range(1, nsteps + 1):
+        sim.step(1)
+        oracle.step(p, ref, 1)
+        compare(fields_np(sim), 0, ref, tol, tol, tol, what=f"{what} step {k}")
+    sim.close()
+    return ref
+
+
+def test_standing_wave_first_steps():
+    """64 x 128 standing wave (SRT, EQ): the first four steps (both AA parities)."""
+    s = setups.config("standing-wave-64")
+    p = oracle_params(s)
+    announce("standing wave 64x128, 4 steps from the initial state")
+    _run_pair(p, oracle_state(s, p), 4, "standing-wave")
+
+
+def test_standing_wave_restarts_along_the_run():
+    """Start the GPU from oracle states along 1000 steps of the standing wave and
+    compare the next two steps each time."""
+    s = setups.config("standing-wave-64")
+    p = oracle_params(s)
+    st = oracle_state(s, p)
+    for t in range(0, 1000, 125):
+        announce(f"standing wave restart at step {t}")
+        _run_pair(p, st.copy(), 2, f"standing-wave@{t}")
+        oracle.step(p, st, 125)
+
+
+@pytest.mark.parametrize("scheme", range(5))
+def test_random_states_all_schemes(scheme):
+    """Random interface states with fill levels straddling both thresholds, one
+    periodic and one walled: conversions, refills and excess mass on the first
+    step, for every refilling scheme."""
+    for seed, periodic in ((scheme, (1, 1, 1)), (10 + scheme, (0, 1, 0))):
+        s = setups.random_interface_state(12, 10, 9, seed, periodic=periodic, refill=scheme,
+                                          g=(0.0, 0.0, -1e-4), collision=seed % 2)
+        p = oracle_params(s)
+        st = oracle_state(s, p)
+        announce(f"random state seed {seed} periodic {periodic} scheme {scheme}")
+        ref = _run_pair(p, st, 3, f"random seed {seed} scheme {scheme}")
+        assert ref.counts is not None
+
+
+@pytest.mark.parametrize("scheme", range(5))
+def test_dam_break_small_all_schemes(scheme):
+    """Small 3-D dam break (TRT, walls): 40 steps of collapse with conversions."""
+    s = setups.rect_dam_break(40, 6, 24, width=12, height=16, g=2e-4, refill=scheme)
+    p = oracle_params(s)
+    st = oracle_state(s, p)
+    announce(f"dam break 40x6x24 scheme {scheme}")
+    sim = sim_from_states(p, [st])
+    for k in range(40):
+        sim.step(1)
+        oracle.step(p, st, 1)
+        if k % 8 == 7:
+            compare(fields_np(sim), 0, st, 1e-11, 1e-11, 1e-11, what=f"dam break step {k + 1}")
+    sim.close()
+
+
+def test_surface_tension_drop():
+    """Curvature path: a small 3-D drop with surface tension (sigma != 0)."""
+    n = 20
+    c = n / 2
+    sd = lambda x, y, z: np.sqrt((x - c) ** 2 + (y - c) ** 2 + (z - c) ** 2) - 6.0
+    phi = setups.shape_fill(n, n, n, sd).ravel()
+    flags = setups.types_from_phi(phi)
+    setups.close_interface(flags, phi, (n, n, n), (1, 1, 1))
+    phi = np.where(flags == 1, 1.0, np.where(flags == 4, 0.0, phi))
+    p = oracle.Params(n, n, n, periodic=(1, 1, 1), collision=1, omega=1.7, sigma=5e-3)
+    st = oracle.init_state(p, flags, phi, np.ones(n ** 3), np.zeros((3, n ** 3)))
+    announce("drop with surface tension, 10 steps")
+    _run_pair(p, st, 10, "drop")
+
+
+def test_batch_of_domains_with_own_parameters():
+    """Three domains in one launch, each with its own state, omega and gravity."""
+    states, omegas, gravs = [], [1.6, 1.75, 1.9], []
+    for k in range(3):
+        s = setups.random_interface_state(10, 9, 8, 40 + k, periodic=(1, 0, 1))
+        st = oracle_state(s, oracle_params(s))
+        states.append(st)
+        gravs.append((0.0, -1e-4 * (k + 1), 0.0))
+    p = oracle_params(s)
+    sim = sim_from_states(p, states, omega_b=omegas, gravity_b=gravs)
+    announce("batch of 3 domains")
+    sim.step(2)
+    got = fields_np(sim)
+    for k in range(3):
+        pk = oracle.Params(**{**p.__dict__, "omega": omegas[k], "g": gravs[k]})
+        oracle.step(pk, states[k], 2)
+        compare(got, k, states[k], what=f"domain {k}")
+
+
+def test_graph_replay_matches_direct_launches():
+    s = setups.rect_dam_break(40, 6, 24, width=12, height=16, g=2e-4, refill=2)
+    p = oracle_params(s)
+    st = oracle_state(s, p)
+    a = sim_from_states(p, [st])
+    b = sim_from_states(p, [st])
+    b.use_graphs(False)
+    announce("graph vs direct launches, 30 steps")
+    a.step(30)
+    b.step(30)
+    fa, fb = fields_np(a), fields_np(b)
+    for k in fa:
+        assert np.array_equal(fa[k], fb[k]), k
+
+
+def test_mass_conservation_and_diagnostics():
+    """Total mass from the device diagnostics stays within 1e-12 relative over
+    500 dam-break steps (FP64) and matches the oracle's total."""
+    s = setups.rect_dam_break(40, 6, 24, width=12, height=16, g=2e-4)
+    p = oracle_params(s)
+    st = oracle_state(s, p)
+    M0 = oracle.total_mass(p, st)
+    sim = sim_from_states(p, [st])
+    d0 = sim.diagnostics()[0]
+    assert abs(d0["total_mass"] - M0) < 1e-12 * M0
+    announce("mass conservation 500 steps")
+    sim.step(500)
+    d = sim.diagnostics()[0]
+    assert abs(d["total_mass"] - M0) < 1e-12 * M0
+    assert d["finite"] and d["stable"]
