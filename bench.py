@@ -1,0 +1,235 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the MI355X FSLBM step; prints ONE JSON line.
+
+Workload (default): the cylindrical dam break, 512 x 512 x 96 cells (~25M),
+liquid cylinder r = 64, h = 80 at the centre, D3Q19 TRT omega = 1.9,
+g = 2e-5 along -z, walls on all sides, EQ refilling, FP32 shifted-PDF
+storage with FP64 mass / fill level.  Synthetic, seeded geometry (no dataset).
+
+value      MLUPS_fluid = (liquid + interface cells) x steps / time, whole job,
+           state resident in HBM, steps replayed as HIP graphs.
+roofline   the bulk stream-collide kernel: algorithmic bytes per launch (one
+           flag byte per cell + 19 PDFs read and written per fluid cell +
+           40 B per interface cell) / its average duration, measured live with
+           HIP events around every bulk launch of a second pass of steps.
+cpu_baseline  the FP64 CPU oracle (single thread) on a bounded sample of the
+           same workload.
+variants   other storage types, the dense pool-wave case (83% fluid), and the
+           reduced-precision error against the FP64 run.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+HBM_PEAK_GBS = 8000.0
+METRIC = "FSLBM MLUPS + HBM GB/s (% peak); FP16/FP32-store vs FP64 at stated error"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "bulk_kernel_hbm_traffic.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_2207_14496_amd", "csrc", "step_kernels.hip")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def bulk_bytes(n_cells, n_fluid, n_if, storage_bytes):
+    """Algorithmic HBM bytes of one bulk stream-collide launch."""
+    return n_cells * 1 + n_fluid * 38 * storage_bytes + n_if * 40
+
+
+def kernel_src_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(workload, storage_name):
+    """HBM bytes per bulk launch from committed rocprofv3 PMC summaries, or None
+    if absent or taken on a different kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    want = kernel_src_hash()
+    for line in open(TRAFFIC_FILE):
+        if not line.startswith("traffic "):
+            continue
+        kv = dict(tok.split("=", 1) for tok in line.split()[1:])
+        if kv.get("workload") == workload and kv.get("storage") == storage_name:
+            if kv.get("kernel_src") != want:
+                return None
+            return float(kv["bytes_per_launch"])
+    return None
+
+
+def run_case(fslbm, setup, storage, steps, warmup, timed_steps, use_graphs=True):
+    import torch
+    sim = fslbm.from_setup(setup, storage=storage)
+    sim.use_graphs(use_graphs)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    d0 = sim.diagnostics()[0]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    sim.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    d1 = sim.diagnostics()[0]
+    fluid = 0.5 * ((d0["n_liquid"] + d0["n_interface"]) + (d1["n_liquid"] + d1["n_interface"]))
+    n_if = 0.5 * (d0["n_interface"] + d1["n_interface"])
+    bulk_ms, total_ms = sim.step_timed(timed_steps)
+    d2 = sim.diagnostics()[0]
+    out = dict(sim=sim, ms=ms, fluid=fluid, n_if=n_if, d0=d0, d1=d1, d2=d2,
+               bulk_ms_avg=bulk_ms / timed_steps, timed_total_ms=total_ms)
+    return out
+
+
+def roofline(setup, storage_bytes, r, traffic):
+    nbytes = bulk_bytes(setup.N, r["fluid"], r["n_if"], storage_bytes)
+    achieved = nbytes / (r["bulk_ms_avg"] * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "algorithmic_bytes_per_launch": int(nbytes),
+            "kernel_avg_ms": round(r["bulk_ms_avg"], 5)}
+
+
+def cpu_baseline(setup, target_s=20.0):
+    """The oracle as it stands, single-threaded, on whole steps of the same
+    initial state, stopping after ~target_s seconds of CPU work."""
+    sys.path.insert(0, ROOT)
+    import oracle
+    p = oracle.Params(setup.nx, setup.ny, setup.nz, tuple(setup.periodic), setup.collision,
+                      setup.refill, setup.omega, setup.trt_lambda, tuple(setup.g), setup.sigma,
+                      setup.p_volume, setup.eps_phi)
+    st = oracle.init_state(p, setup.flags, setup.phi, setup.rho, setup.u)
+    fluid = setup.fluid_cells()
+    oracle.step(p, st, 1)   # builds the neighbour table, warms caches
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        oracle.step(p, st, 1)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el > target_s or steps >= 50:
+            break
+    return {"value": round(fluid * steps / el / 1e6, 3), "unit": "MLUPS (fluid cells)",
+            "cores": 1, "kind": "oracle",
+            "sample": f"{steps} whole steps of the same {setup.nx}x{setup.ny}x{setup.nz} "
+                      f"initial state after 1 untimed step ({el:.1f} s, FP64, single thread, "
+                      f"host nproc={os.cpu_count()})"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--storage", default="f32", choices=["f64", "f32", "f16", "bf16"])
+    ap.add_argument("--workload", default="cyl-dam-break",
+                    choices=["cyl-dam-break", "pool-wave", "rect-dam-break", "drop-impact"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--variant-steps", type=int, default=300)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py: this build runs on exactly one GPU (the path has no multi-GPU "
+              "sharding); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    sys.path.insert(0, ROOT)
+    import torch
+    from paper_2207_14496_amd import fslbm, setups
+
+    storage = {"f64": fslbm.F64, "f32": fslbm.F32, "f16": fslbm.F16, "bf16": fslbm.BF16}[args.storage]
+    sb = fslbm.STORAGE_BYTES[storage]
+    log(f"building workload {args.workload}")
+    setup = setups.config(args.workload)
+    log(f"{setup.nx}x{setup.ny}x{setup.nz}: {setup.fluid_cells()} fluid cells; warmup "
+        f"{args.warmup}, timed {args.steps} steps, storage {args.storage}")
+    timed_k = max(1, min(args.steps, 500))
+    r = run_case(fslbm, setup, storage, args.steps, args.warmup, timed_k)
+    ms_step = r["ms"] / args.steps
+    value = r["fluid"] * args.steps / (r["ms"] * 1e-3) / 1e6
+    mlups_domain = setup.N * args.steps / (r["ms"] * 1e-3) / 1e6
+    log(f"{value:.1f} MLUPS_fluid, {mlups_domain:.1f} MLUPS_domain, {ms_step * 1e3:.1f} us/step, "
+        f"bulk kernel {r['bulk_ms_avg'] * 1e3:.1f} us")
+    traffic = measured_traffic(args.workload, args.storage)
+    rl = roofline(setup, sb, r, traffic)
+    mass_drift = (r["d2"]["total_mass"] - r["d0"]["total_mass"]) / r["d0"]["total_mass"]
+    r["sim"].close()
+    del r["sim"]
+    torch.cuda.empty_cache()
+
+    result = {
+        "metric": METRIC, "value": round(value, 2), "unit": "MLUPS (fluid-cell updates/s)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": args.storage, "data": "synthetic",
+        "config": {"workload": f"{args.workload} {setup.nx}x{setup.ny}x{setup.nz} D3Q19 "
+                               f"{'TRT' if setup.collision else 'SRT'} omega={setup.omega} "
+                               f"g={abs(sum(setup.g)):g} EQ refill, {args.storage} shifted PDFs, "
+                               f"f64 mass/fill level",
+                   "cells": setup.N, "fluid_cells_avg": int(r["fluid"]),
+                   "interface_cells_avg": int(r["n_if"]),
+                   "mlups_domain": round(mlups_domain, 1), "mass_drift_rel": mass_drift,
+                   "graphs": True, "parallelism": "single GPU"},
+        "roofline": rl,
+    }
+
+    if not args.no_variants:
+        result["variants"] = variants(fslbm, setups, torch, args)
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle")
+        result["cpu_baseline"] = cpu_baseline(setup)
+    print(json.dumps(result), flush=True)
+
+
+def variants(fslbm, setups, torch, args):
+    """Other storage types on the same workload, the dense pool case, and the
+    reduced-precision error against the FP64 run after the same steps."""
+    out = []
+    ks = args.variant_steps
+    for wl in ("cyl-dam-break", "pool-wave"):
+        log(f"variants on {wl}")
+        setup = setups.config(wl)
+        ref = None
+        for name, st in (("f64", fslbm.F64), ("f32", fslbm.F32), ("f16", fslbm.F16),
+                         ("bf16", fslbm.BF16)):
+            r = run_case(fslbm, setup, st, ks, 20, min(ks, 200))
+            sb = fslbm.STORAGE_BYTES[st]
+            rl = roofline(setup, sb, r, measured_traffic(wl, name))
+            rec = {"workload": wl, "storage": name, "steps": ks,
+                   "mlups_fluid": round(r["fluid"] * ks / (r["ms"] * 1e-3) / 1e6, 1),
+                   "mlups_domain": round(setup.N * ks / (r["ms"] * 1e-3) / 1e6, 1),
+                   "ms_per_step": round(r["ms"] / ks, 5), "bulk_gbs": rl["achieved"],
+                   "bulk_frac": rl["frac"], "bulk_kernel_ms": rl["kernel_avg_ms"]}
+            f = r["sim"].read(("phi", "flags"))
+            phi = f["phi"][0]
+            d = r["d2"]
+            rec["mass_drift_rel"] = (d["total_mass"] - r["d0"]["total_mass"]) / r["d0"]["total_mass"]
+            if ref is None:
+                ref = {"phi": phi.clone(), "flags": f["flags"][0].clone()}
+            else:
+                dphi = (phi - ref["phi"]).abs()
+                nz, ny, nx = setup.nz, setup.ny, setup.nx
+                h = phi.reshape(nz, ny, nx).clamp(0, 1).sum(0)
+                h_ref = ref["phi"].reshape(nz, ny, nx).clamp(0, 1).sum(0)
+                rec["vs_f64"] = {"max_abs_phi": float(dphi.max()),
+                                 "mean_abs_phi": float(dphi.mean()),
+                                 "max_abs_column_height": float((h - h_ref).abs().max()),
+                                 "flag_mismatch_cells": int((f["flags"][0] != ref["flags"]).sum())}
+            r["sim"].close()
+            del r["sim"], f
+            torch.cuda.empty_cache()
+            out.append(rec)
+            log(f"  {wl} {name}: {rec['mlups_fluid']} MLUPS_fluid, bulk {rec['bulk_gbs']} GB/s "
+                f"({rec['bulk_frac'] * 100:.1f}%)")
+    return out
+
+
+if __name__ == "__main__":
+    main()

@@ -157,6 +157,13 @@ fslbm_status fslbm_init(const fslbm_params *params, void *workspace, size_t byte
  * Asynchronous: device-side failures surface at the next synchronising call. */
 fslbm_status fslbm_step(fslbm_ctx *ctx, int32_t nsteps);
 
+/* Run nsteps >= 1 full time steps (a)-(e) with direct kernel launches and HIP
+ * events recorded on the context's stream right before and after the bulk
+ * stream-collide kernel of every step.  Synchronises, then returns (HOST
+ * doubles, milliseconds) the summed duration of the bulk kernels and the wall
+ * time of the whole sequence.  The state advances exactly as fslbm_step. */
+fslbm_status fslbm_step_timed(fslbm_ctx *ctx, int32_t nsteps, double *bulk_ms, double *total_ms);
+
 /* Select the refilling scheme (fslbm_refill) used by subsequent steps. */
 fslbm_status fslbm_refill_scheme(fslbm_ctx *ctx, int32_t scheme);
 

@@ -511,6 +511,42 @@ fslbm_status fslbm_step(fslbm_ctx *c, int32_t nsteps) {
     return FSLBM_OK;
 }
 
+fslbm_status fslbm_step_timed(fslbm_ctx *c, int32_t nsteps, double *bulk_ms, double *total_ms) {
+    if (!c) return FSLBM_EINVAL;
+    if (c->status != FSLBM_OK) return c->status;
+    if (nsteps < 1 || !bulk_ms || !total_ms) return fail(c, FSLBM_EINVAL, "nsteps >= 1 and outputs required");
+    std::vector<hipEvent_t> ev(size_t(2) * nsteps + 2, nullptr);
+    bool ok = true;
+    for (auto &e : ev)
+        if (ok) ok = hip_ok(c, hipEventCreate(&e), "hipEventCreate");
+    if (ok) ok = hip_ok(c, hipEventRecord(ev[2 * nsteps], c->stream), "hipEventRecord");
+    for (int32_t s = 0; ok && s < nsteps; ++s) {
+        BulkEvents be{ev[2 * s], ev[2 * s + 1]};
+        launch_step(make_args(c, int(c->t & 1)), c->p.storage, c->p.collision, c->p.refill, c->stream, &be);
+        ok = hip_ok(c, hipGetLastError(), "step kernel launch");
+        if (ok) ++c->t;
+    }
+    if (ok) ok = hip_ok(c, hipEventRecord(ev[2 * nsteps + 1], c->stream), "hipEventRecord") &&
+                 hip_ok(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    double bulk = 0.0, total = 0.0;
+    for (int32_t s = 0; ok && s < nsteps; ++s) {
+        float ms = 0.0f;
+        ok = hip_ok(c, hipEventElapsedTime(&ms, ev[2 * s], ev[2 * s + 1]), "hipEventElapsedTime");
+        bulk += ms;
+    }
+    if (ok) {
+        float ms = 0.0f;
+        ok = hip_ok(c, hipEventElapsedTime(&ms, ev[2 * nsteps], ev[2 * nsteps + 1]), "hipEventElapsedTime");
+        total = ms;
+    }
+    for (auto &e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (!ok) return c->status;
+    *bulk_ms = bulk;
+    *total_ms = total;
+    return device_errors_ok(c) ? FSLBM_OK : c->status;
+}
+
 fslbm_status fslbm_refill_scheme(fslbm_ctx *c, int32_t scheme) {
     if (!c) return FSLBM_EINVAL;
     if (c->status != FSLBM_OK) return c->status;

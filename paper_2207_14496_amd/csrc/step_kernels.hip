@@ -648,7 +648,8 @@ static int list_blocks(long long cap) {
 }
 
 template <int ST>
-static void launch_step_t(const StepArgs &a, int collision, int scheme, hipStream_t s) {
+static void launch_step_t(const StepArgs &a, int collision, int scheme, hipStream_t s,
+                          const BulkEvents *ev) {
     const int lb = list_blocks(a.cap);
     if (a.rhoG) {
         hipLaunchKernelGGL(k_band, dim3(lb), dim3(256), 0, s, a);
@@ -657,6 +658,7 @@ static void launch_step_t(const StepArgs &a, int collision, int scheme, hipStrea
     }
     hipLaunchKernelGGL(k_mass_exchange<ST>, dim3(lb), dim3(256), 0, s, a);
     const unsigned nblk = unsigned((a.g.BN + 255) / 256);
+    if (ev) (void)hipEventRecord(ev->before, s);
     if (collision == 0) {
         if (a.parity == 0) hipLaunchKernelGGL((k_stream_collide<ST, 0, 0>), dim3(nblk), dim3(256), 0, s, a);
         else hipLaunchKernelGGL((k_stream_collide<ST, 0, 1>), dim3(nblk), dim3(256), 0, s, a);
@@ -664,6 +666,7 @@ static void launch_step_t(const StepArgs &a, int collision, int scheme, hipStrea
         if (a.parity == 0) hipLaunchKernelGGL((k_stream_collide<ST, 1, 0>), dim3(nblk), dim3(256), 0, s, a);
         else hipLaunchKernelGGL((k_stream_collide<ST, 1, 1>), dim3(nblk), dim3(256), 0, s, a);
     }
+    if (ev) (void)hipEventRecord(ev->after, s);
     hipLaunchKernelGGL(k_resolve, dim3(lb), dim3(256), 0, s, a);
     switch (scheme) {
         case 0: hipLaunchKernelGGL((k_refill<ST, 0>), dim3(lb), dim3(256), 0, s, a); break;
@@ -682,18 +685,19 @@ static void launch_step_t(const StepArgs &a, int collision, int scheme, hipStrea
 #if defined(FSLBM_UNIT_STORAGE)
 template <>
 void launch_step_storage<FSLBM_UNIT_STORAGE>(const StepArgs &a, int collision, int scheme,
-                                             hipStream_t s) {
-    launch_step_t<FSLBM_UNIT_STORAGE>(a, collision, scheme, s);
+                                             hipStream_t s, const BulkEvents *ev) {
+    launch_step_t<FSLBM_UNIT_STORAGE>(a, collision, scheme, s, ev);
 }
 #endif
 
 #if defined(FSLBM_UNIT_DISPATCH)
-void launch_step(const StepArgs &a, int storage, int collision, int scheme, hipStream_t s) {
+void launch_step(const StepArgs &a, int storage, int collision, int scheme, hipStream_t s,
+                 const BulkEvents *ev) {
     switch (storage) {
-        case ST_F64: launch_step_storage<ST_F64>(a, collision, scheme, s); break;
-        case ST_F32: launch_step_storage<ST_F32>(a, collision, scheme, s); break;
-        case ST_F16: launch_step_storage<ST_F16>(a, collision, scheme, s); break;
-        default: launch_step_storage<ST_BF16>(a, collision, scheme, s); break;
+        case ST_F64: launch_step_storage<ST_F64>(a, collision, scheme, s, ev); break;
+        case ST_F32: launch_step_storage<ST_F32>(a, collision, scheme, s, ev); break;
+        case ST_F16: launch_step_storage<ST_F16>(a, collision, scheme, s, ev); break;
+        default: launch_step_storage<ST_BF16>(a, collision, scheme, s, ev); break;
     }
 }
 #endif

@@ -27,7 +27,8 @@ STORAGE_NAMES = {F64: "f64", F32: "f32", F16: "f16", BF16: "bf16"}
 STORAGE_BYTES = {F64: 8, F32: 4, F16: 2, BF16: 2}
 
 # Exported symbols, in the order include/fslbm.h declares them.
-SYMBOLS = ["fslbm_workspace_bytes", "fslbm_init", "fslbm_step", "fslbm_refill_scheme",
+SYMBOLS = ["fslbm_workspace_bytes", "fslbm_init", "fslbm_step", "fslbm_step_timed",
+           "fslbm_refill_scheme",
            "fslbm_use_graphs", "fslbm_set_stream", "fslbm_read_fields", "fslbm_diagnostics",
            "fslbm_last_error", "fslbm_destroy"]
 
@@ -71,6 +72,7 @@ def lib() -> ctypes.CDLL:
         L.fslbm_workspace_bytes.argtypes = [P(CParams), P(ctypes.c_size_t)]
         L.fslbm_init.argtypes = [P(CParams), vp, ctypes.c_size_t, vp, vp, vp, vp, vp, vp, P(vp)]
         L.fslbm_step.argtypes = [vp, ctypes.c_int32]
+        L.fslbm_step_timed.argtypes = [vp, ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_double)]
         L.fslbm_refill_scheme.argtypes = [vp, ctypes.c_int32]
         L.fslbm_use_graphs.argtypes = [vp, ctypes.c_int32]
         L.fslbm_set_stream.argtypes = [vp, vp]
@@ -80,7 +82,8 @@ def lib() -> ctypes.CDLL:
         L.fslbm_last_error.restype = ctypes.c_char_p
         L.fslbm_destroy.argtypes = [vp]
         L.fslbm_destroy.restype = None
-        for name in ("fslbm_workspace_bytes", "fslbm_init", "fslbm_step", "fslbm_refill_scheme",
+        for name in ("fslbm_workspace_bytes", "fslbm_init", "fslbm_step", "fslbm_step_timed",
+                     "fslbm_refill_scheme",
                      "fslbm_use_graphs", "fslbm_set_stream", "fslbm_read_fields",
                      "fslbm_diagnostics"):
             getattr(L, name).restype = ctypes.c_int
@@ -191,6 +194,15 @@ class Simulation:
     def step(self, nsteps: int = 1):
         _check(lib().fslbm_step(self._ctx, int(nsteps)), self._ctx)
         self.steps_done += int(nsteps)
+
+    def step_timed(self, nsteps: int):
+        """Run nsteps with events around every bulk stream-collide kernel; returns
+        (summed bulk-kernel ms, wall ms of the sequence).  Synchronises."""
+        bulk, total = ctypes.c_double(), ctypes.c_double()
+        _check(lib().fslbm_step_timed(self._ctx, int(nsteps), ctypes.byref(bulk),
+                                      ctypes.byref(total)), self._ctx)
+        self.steps_done += int(nsteps)
+        return bulk.value, total.value
 
     def set_refill(self, scheme: int):
         _check(lib().fslbm_refill_scheme(self._ctx, int(scheme)), self._ctx)
