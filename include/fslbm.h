@@ -188,6 +188,18 @@ fslbm_status fslbm_read_fields(fslbm_ctx *ctx, uint32_t field_mask, void *const 
  * of Sec. 4). */
 fslbm_status fslbm_diagnostics(fslbm_ctx *ctx, fslbm_diag *out);
 
+/* Conversion activity of the most recent step, summed over all domains. */
+typedef struct fslbm_step_stats {
+    int64_t interface_cells;  /* interface cells after the step                  */
+    int64_t new_from_gas;     /* gas cells that became interface (refilled)      */
+    int64_t from_liquid;      /* liquid cells that became interface              */
+    int64_t converted;        /* interface cells that became liquid or gas       */
+} fslbm_step_stats;
+
+/* Fill *out with the conversion activity of the last step (zeros before the
+ * first step).  Synchronises. */
+fslbm_status fslbm_last_step_stats(fslbm_ctx *ctx, fslbm_step_stats *out);
+
 /* Text of the first error seen by this context (or by the last failed init
  * when ctx is NULL).  Never NULL. */
 const char *fslbm_last_error(const fslbm_ctx *ctx);

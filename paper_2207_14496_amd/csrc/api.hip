@@ -27,7 +27,7 @@ size_t storage_bytes(int st) { return st == FSLBM_F64 ? 8 : (st == FSLBM_F32 ? 4
 
 // Byte offsets of every array inside the caller's workspace.
 struct Layout {
-    size_t pdf, flags, m, phi, uif, mex, rhoG, normal, band;
+    size_t pdf, fo, flags, m, phi, mex, rhoG, normal, band;
     size_t lists[7];   // if0, if1, newg, froml, conv0, conv1, band
     size_t cnt, nif, res, omega, grav, diag_d, diag_i;
     size_t total;
@@ -41,8 +41,8 @@ bool make_layout(const fslbm_params &p, Layout &L) {
     L.pdf = take(size_t(BN) * Q * storage_bytes(p.storage));
     L.flags = take(size_t(BN) + 4);
     L.m = take(size_t(BN) * 8);
-    L.phi = take(size_t(BN) * 8);
-    L.uif = take(size_t(BN) * 24);
+    L.phi = take(size_t(BN) * 16);   // two buffers
+    L.fo = take(size_t(BN) * 18 * storage_bytes(p.storage));
     L.mex = take(size_t(BN) * 8);
     bool surf = p.sigma != 0.0;
     L.rhoG = surf ? take(size_t(BN) * 8) : 0;
@@ -65,6 +65,7 @@ const char *validate(const fslbm_params *p) {
     if (p->nx < 1 || p->ny < 1 || p->nz < 1 || p->batch < 1) return "sizes must be >= 1";
     long long BN = (long long)p->nx * p->ny * p->nz * p->batch;
     if (BN >= (1LL << 31) - 64) return "more than 2^31 cells in total";
+    if ((long long)p->nx * p->ny * p->nz * Q >= (1LL << 32)) return "more than 2^32 / 19 cells per domain";
     if (!(p->omega > 0.0 && p->omega < 2.0)) return "omega must lie in (0, 2)";
     if (p->collision != FSLBM_SRT && p->collision != FSLBM_TRT) return "unknown collision";
     if (p->storage < FSLBM_F64 || p->storage > FSLBM_BF16) return "unknown storage";
@@ -112,7 +113,8 @@ __global__ void k_init_cells(InitArgs ia) {
     }
     if (err) atomicOr(a.cnt + C_ERR, err);
     a.flags[gid] = fl;
-    a.phi[gid] = ph;
+    a.phi_cur[gid] = ph;
+    a.phi_next[gid] = ph;
     bool fluid = fl != F_GAS;
     double d[Q];
     if (!fluid) {
@@ -134,6 +136,12 @@ __global__ void k_init_cells(InitArgs ia) {
     typename C::M *base = pdf + (long long)c.b * Q * N + c.n;
 #pragma unroll
     for (int i = 0; i < Q; ++i) C::store(base + opp(i) * N, typename C::T(d[i]));
+    if (fl == F_IF) {
+        // outgoing populations of interface cells, read by the next mass exchange
+        typename C::M *fo = static_cast<typename C::M *>(a.fo);
+#pragma unroll
+        for (int i = 1; i < Q; ++i) C::store(fo + (long long)(i - 1) * a.g.BN + gid, typename C::T(d[i]));
+    }
     double m = 0.0;
     if (fl == F_IF) {
         if (ia.mass_in) {
@@ -198,15 +206,15 @@ __global__ void k_read(ReadArgs r) {
     bool fluid = fl != F_GAS;
     if (r.mask & FSLBM_FIELD_FLAGS) r.flags[gid] = fl;
     if (r.mask & FSLBM_FIELD_MASS) r.mass[gid] = fl == F_IF ? a.m[gid] : 0.0;
-    if (r.mask & FSLBM_FIELD_PHI) r.phi[gid] = a.phi[gid];
+    if (r.mask & FSLBM_FIELD_PHI) r.phi[gid] = a.phi_cur[gid];
     if (r.mask & (FSLBM_FIELD_PDF | FSLBM_FIELD_RHO | FSLBM_FIELD_VEL)) {
         double d[Q];
         if (fluid) {
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
-                Slot s = slot_of(a.g, r.layoutB, c, gid, i);
                 using Cd = Codec<ST>;
-                d[i] = double(Cd::load(static_cast<const typename Cd::M *>(a.pdf) + slot_index(a.g, s)));
+                d[i] = double(Cd::load(static_cast<const typename Cd::M *>(a.pdf) +
+                                       slot_flat(a.g, r.layoutB, c, i)));
             }
         } else {
 #pragma unroll
@@ -252,9 +260,9 @@ __global__ __launch_bounds__(256) void k_diag_partial(StepArgs a, int layoutB, d
         bool fin = true;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            Slot s = slot_of(a.g, layoutB, c, gid, i);
             using Cd = Codec<ST>;
-            d[i] = double(Cd::load(static_cast<const typename Cd::M *>(a.pdf) + slot_index(a.g, s)));
+            d[i] = double(Cd::load(static_cast<const typename Cd::M *>(a.pdf) +
+                                   slot_flat(a.g, layoutB, c, i)));
             fin &= isfinite(d[i]);
         }
         const double *gr = a.grav + 3 * b;
@@ -262,7 +270,7 @@ __global__ __launch_bounds__(256) void k_diag_partial(StepArgs a, int layoutB, d
         moments_post(d, gr[0], gr[1], gr[2], rho, ux, uy, uz);
         double sp = sqrt(ux * ux + uy * uy + uz * uz);
         if (fl == F_LIQ) { ++nl; mass += rho; }
-        else { ++ni; mass += a.m[gid]; fin &= isfinite(a.m[gid]) && isfinite(a.phi[gid]); }
+        else { ++ni; mass += a.m[gid]; fin &= isfinite(a.m[gid]) && isfinite(a.phi_cur[gid]); }
         vmax = fin ? (sp > vmax ? sp : vmax) : vmax;
         bad += !fin || !isfinite(sp);
     }
@@ -299,6 +307,7 @@ struct fslbm_ctx {
     long long t = 0;                 // steps done
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
+    SideStream side{nullptr, nullptr, nullptr};   // interface kernel beside the bulk kernel
     bool graphs = true;
     hipGraphExec_t exec[2] = {nullptr, nullptr};
     fslbm_status status = FSLBM_OK;
@@ -317,11 +326,16 @@ StepArgs make_args(fslbm_ctx *c, int parity) {
     for (int k = 0; k < 3; ++k) a.g.per[k] = p.periodic[k];
     a.g.N = (long long)p.nx * p.ny * p.nz;
     a.g.BN = a.g.N * p.batch;
+    a.g.dx = FastDiv::make(uint32_t(p.nx));
+    a.g.dy = FastDiv::make(uint32_t(p.ny));
+    a.g.dN = FastDiv::make(uint32_t(a.g.N));
     a.pdf = c->ws + c->L.pdf;
     a.flags = at<uint8_t>(c, c->L.flags);
     a.m = at<double>(c, c->L.m);
-    a.phi = at<double>(c, c->L.phi);
-    a.uif = at<double>(c, c->L.uif);
+    // fill level: buffer (steps done) mod 2 holds the current one
+    a.phi_cur = at<double>(c, c->L.phi) + size_t(parity) * size_t(a.g.BN);
+    a.phi_next = at<double>(c, c->L.phi) + size_t(1 - parity) * size_t(a.g.BN);
+    a.fo = c->ws + c->L.fo;
     a.mex = at<double>(c, c->L.mex);
     bool surf = p.sigma != 0.0;
     a.rhoG = surf ? at<double>(c, c->L.rhoG) : nullptr;
@@ -392,7 +406,7 @@ bool capture(fslbm_ctx *c, int parity) {
     if (!hip_ok(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal),
                 "hipStreamBeginCapture"))
         return false;
-    launch_step(make_args(c, parity), c->p.storage, c->p.collision, c->p.refill, c->cap_stream);
+    launch_step(make_args(c, parity), c->p.storage, c->p.collision, c->p.refill, c->cap_stream, c->side);
     hipError_t le = hipGetLastError();
     hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
     if (!hip_ok(c, le, "kernel launch (capture)") || !hip_ok(c, e, "hipStreamEndCapture")) return false;
@@ -449,7 +463,10 @@ fslbm_status fslbm_init(const fslbm_params *params, void *workspace, size_t byte
             c->grav_h[3 * b + k] = params->gravity_b ? params->gravity_b[3 * b + k] : params->gravity[k];
     }
     StepArgs a = make_args(c, 0);
-    bool ok = hip_ok(c, hipMemcpyAsync(at<double>(c, c->L.omega), c->omega_h.data(), 8 * B,
+    bool ok = hip_ok(c, hipStreamCreateWithFlags(&c->side.stream, hipStreamNonBlocking), "hipStreamCreate") &&
+              hip_ok(c, hipEventCreateWithFlags(&c->side.fork, hipEventDisableTiming), "hipEventCreate") &&
+              hip_ok(c, hipEventCreateWithFlags(&c->side.join, hipEventDisableTiming), "hipEventCreate");
+    ok = ok && hip_ok(c, hipMemcpyAsync(at<double>(c, c->L.omega), c->omega_h.data(), 8 * B,
                                        hipMemcpyHostToDevice, c->stream), "hipMemcpy(omega)") &&
               hip_ok(c, hipMemcpyAsync(at<double>(c, c->L.grav), c->grav_h.data(), 24 * B,
                                        hipMemcpyHostToDevice, c->stream), "hipMemcpy(gravity)") &&
@@ -457,7 +474,8 @@ fslbm_status fslbm_init(const fslbm_params *params, void *workspace, size_t byte
               hip_ok(c, hipMemsetAsync(a.nif_dom, 0, 8 * B, c->stream), "hipMemset") &&
               hip_ok(c, hipMemsetAsync(a.res, 0, 16 * B, c->stream), "hipMemset") &&
               hip_ok(c, hipMemsetAsync(a.mex, 0, size_t(a.g.BN) * 8, c->stream), "hipMemset") &&
-              hip_ok(c, hipMemsetAsync(a.uif, 0, size_t(a.g.BN) * 24, c->stream), "hipMemset");
+              hip_ok(c, hipMemsetAsync(a.fo, 0, size_t(a.g.BN) * 18 * storage_bytes(c->p.storage), c->stream),
+                     "hipMemset");
     if (ok && a.band)
         ok = hip_ok(c, hipMemsetAsync(a.band, 0, size_t((a.g.BN + 31) / 32) * 4, c->stream), "hipMemset") &&
              hip_ok(c, hipMemsetAsync(a.rhoG, 0, size_t(a.g.BN) * 8, c->stream), "hipMemset") &&
@@ -486,7 +504,7 @@ fslbm_status fslbm_init(const fslbm_params *params, void *workspace, size_t byte
     if (!ok) {
         g_init_error = c->err;
         fslbm_status s = c->status;
-        delete c;
+        fslbm_destroy(c);
         return s;
     }
     *out = c;
@@ -503,7 +521,7 @@ fslbm_status fslbm_step(fslbm_ctx *c, int32_t nsteps) {
             if (!c->exec[parity] && !capture(c, parity)) return c->status;
             if (!hip_ok(c, hipGraphLaunch(c->exec[parity], c->stream), "hipGraphLaunch")) return c->status;
         } else {
-            launch_step(make_args(c, parity), c->p.storage, c->p.collision, c->p.refill, c->stream);
+            launch_step(make_args(c, parity), c->p.storage, c->p.collision, c->p.refill, c->stream, c->side);
             if (!hip_ok(c, hipGetLastError(), "step kernel launch")) return c->status;
         }
         ++c->t;
@@ -522,7 +540,8 @@ fslbm_status fslbm_step_timed(fslbm_ctx *c, int32_t nsteps, double *bulk_ms, dou
     if (ok) ok = hip_ok(c, hipEventRecord(ev[2 * nsteps], c->stream), "hipEventRecord");
     for (int32_t s = 0; ok && s < nsteps; ++s) {
         BulkEvents be{ev[2 * s], ev[2 * s + 1]};
-        launch_step(make_args(c, int(c->t & 1)), c->p.storage, c->p.collision, c->p.refill, c->stream, &be);
+        launch_step(make_args(c, int(c->t & 1)), c->p.storage, c->p.collision, c->p.refill, c->stream,
+                    c->side, &be);
         ok = hip_ok(c, hipGetLastError(), "step kernel launch");
         if (ok) ++c->t;
     }
@@ -660,6 +679,28 @@ fslbm_status fslbm_diagnostics(fslbm_ctx *c, fslbm_diag *out) {
     return unstable ? FSLBM_EUNSTABLE : FSLBM_OK;
 }
 
+fslbm_status fslbm_last_step_stats(fslbm_ctx *c, fslbm_step_stats *out) {
+    if (!c) return FSLBM_EINVAL;
+    if (c->status != FSLBM_OK) return c->status;
+    if (!out) return fail(c, FSLBM_EINVAL, "out is NULL");
+    int32_t cnt[C_COUNT];
+    if (!hip_ok(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize") ||
+        !hip_ok(c, hipMemcpy(cnt, at<int32_t>(c, c->L.cnt), sizeof cnt, hipMemcpyDeviceToHost),
+                "hipMemcpy(counters)"))
+        return c->status;
+    *out = fslbm_step_stats{};
+    if (c->t == 0) {
+        out->interface_cells = cnt[C_IF0];
+        return FSLBM_OK;
+    }
+    const int p = int((c->t - 1) & 1);   // parity of the last step
+    out->interface_cells = cnt[C_IF0 + (1 - p)];
+    out->new_from_gas = cnt[C_NEWG];
+    out->from_liquid = cnt[C_FROML];
+    out->converted = cnt[C_CONV0 + p];
+    return FSLBM_OK;
+}
+
 const char *fslbm_last_error(const fslbm_ctx *c) {
     return c ? c->err.c_str() : g_init_error.c_str();
 }
@@ -668,6 +709,9 @@ void fslbm_destroy(fslbm_ctx *c) {
     if (!c) return;
     drop_graphs(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->side.stream) (void)hipStreamDestroy(c->side.stream);
+    if (c->side.fork) (void)hipEventDestroy(c->side.fork);
+    if (c->side.join) (void)hipEventDestroy(c->side.join);
     delete c;
 }
 

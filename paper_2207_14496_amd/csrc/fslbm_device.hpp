@@ -79,43 +79,67 @@ template <> struct Codec<ST_BF16> {
 };
 
 // ------------------------------------------------------------------ geometry
+// Unsigned division of n < 2^31 by an invariant d >= 1 with one 32x32->64
+// multiply and a shift (Granlund & Montgomery): m = ceil(2^(31+l) / d) with
+// l = ceil(log2 d); then n / d == (n * m) >> (31 + l) for every n < 2^31.
+struct FastDiv {
+    uint32_t d, m;
+    int s;
+    __host__ static FastDiv make(uint32_t d) {
+        int l = 0;
+        while ((1ull << l) < d) ++l;
+        FastDiv f;
+        f.d = d;
+        f.m = uint32_t(((1ull << (31 + l)) + d - 1) / d);
+        f.s = 31 + l;
+        return f;
+    }
+    __host__ __device__ __forceinline__ uint32_t div(uint32_t n) const {
+        return uint32_t((uint64_t(n) * m) >> s);
+    }
+};
+
 struct Geom {
     int nx, ny, nz;
     int per[3];
     long long N;      // cells per domain
-    long long BN;     // cells in all domains
+    long long BN;     // cells in all domains (< 2^31)
+    FastDiv dx, dy, dN;
 };
 
-// Neighbour of cell (x,y,z) shifted by (dx,dy,dz) inside the same domain:
-// returns the cell index (domain-local) or -1 for a wall.
-__device__ __forceinline__ long long nb_local(const Geom &g, int x, int y, int z, int dx, int dy,
-                                              int dz) {
-    x += dx; y += dy; z += dz;
+// Neighbour of cell (x,y,z) shifted by (ox,oy,oz) inside the same domain:
+// returns the domain-local cell index or -1 for a wall.
+__device__ __forceinline__ int nb_local(const Geom &g, int x, int y, int z, int ox, int oy, int oz) {
+    x += ox; y += oy; z += oz;
     if (x < 0 || x >= g.nx) { if (!g.per[0]) return -1; x = x < 0 ? x + g.nx : x - g.nx; }
     if (y < 0 || y >= g.ny) { if (!g.per[1]) return -1; y = y < 0 ? y + g.ny : y - g.ny; }
     if (z < 0 || z >= g.nz) { if (!g.per[2]) return -1; z = z < 0 ? z + g.nz : z - g.nz; }
-    return ((long long)z * g.ny + y) * g.nx + x;
+    return (z * g.ny + y) * g.nx + x;
 }
 
 struct Cell {
     int b, x, y, z;
-    long long n;   // domain-local index
+    int n;        // domain-local index
 };
 
 __device__ __forceinline__ Cell decode(const Geom &g, long long gid) {
     Cell c;
-    c.b = int(gid / g.N);
-    c.n = gid - (long long)c.b * g.N;
-    long long r = c.n / g.nx;
-    c.x = int(c.n - r * g.nx);
-    c.y = int(r % g.ny);
-    c.z = int(r / g.ny);
+    uint32_t u = uint32_t(gid);
+    uint32_t b = g.dN.div(u);
+    uint32_t n = u - b * uint32_t(g.N);
+    uint32_t r = g.dx.div(n);
+    uint32_t z = g.dy.div(r);
+    c.b = int(b);
+    c.n = int(n);
+    c.x = int(n - r * uint32_t(g.nx));
+    c.y = int(r - z * uint32_t(g.ny));
+    c.z = int(z);
     return c;
 }
 
 // Global index of the neighbour along c_i, or -1 for a wall.
 __device__ __forceinline__ long long nb_dir(const Geom &g, const Cell &c, int i) {
-    long long k = nb_local(g, c.x, c.y, c.z, cx(i), cy(i), cz(i));
+    int k = nb_local(g, c.x, c.y, c.z, cx(i), cy(i), cz(i));
     return k < 0 ? -1 : (long long)c.b * g.N + k;
 }
 
@@ -123,31 +147,47 @@ __device__ __forceinline__ long long nb_dir(const Geom &g, const Cell &c, int i)
 // In-place streaming (AA pattern, Bailey et al. 2009).  After an even number of
 // steps ("layout A") f*_i(x) sits in slot (opp(i), x).  After an odd number
 // ("layout B") it sits in slot (i, x + c_i), or in (opp(i), x) when x + c_i is
-// a wall.  Slot (d, cell) of domain b is pdf[(b*19 + d)*N + n].
-struct Slot {
-    int d;
-    long long cell;   // global cell index
-};
-__device__ __forceinline__ Slot slot_of(const Geom &g, int layoutB, const Cell &c, long long gid,
-                                        int i) {
-    if (!layoutB) return Slot{opp(i), gid};
-    long long k = nb_dir(g, c, i);
-    if (k < 0) return Slot{opp(i), gid};
-    return Slot{i, k};
+// a wall.  Slot (d, n) of domain b is pdf[(b*19 + d)*N + n].
+
+// The lattice again as tables, for the few places that index a direction with
+// a runtime value (one lane per direction).
+__device__ __constant__ const int8_t k_cx[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+__device__ __constant__ const int8_t k_cy[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+__device__ __constant__ const int8_t k_cz[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+
+// Flat index of the slot holding f*_i of cell c in the given layout, for a
+// runtime direction i.
+__device__ __forceinline__ long long slot_flat_rt(const Geom &g, int layoutB, const Cell &c, int i) {
+    const long long base = (long long)c.b * Q * g.N;
+    if (layoutB && i > 0) {
+        int k = nb_local(g, c.x, c.y, c.z, k_cx[i], k_cy[i], k_cz[i]);
+        if (k >= 0) return base + (long long)i * g.N + k;
+    }
+    const int o = i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1);
+    return base + (long long)o * g.N + c.n;
 }
-__device__ __forceinline__ long long slot_index(const Geom &g, Slot s) {
-    long long b = s.cell / g.N;
-    return (b * Q + s.d) * g.N + (s.cell - b * g.N);
+
+// Flat index of the slot holding f*_i of cell c in the given layout.
+__device__ __forceinline__ long long slot_flat(const Geom &g, int layoutB, const Cell &c, int i) {
+    const long long base = (long long)c.b * Q * g.N;
+    if (layoutB) {
+        int k = nb_local(g, c.x, c.y, c.z, cx(i), cy(i), cz(i));
+        if (k >= 0) return base + (long long)i * g.N + k;
+    }
+    return base + (long long)opp(i) * g.N + c.n;
 }
 
 // ------------------------------------------------------------------ arguments
 struct StepArgs {
     Geom g;
     void *pdf;
+    void *fo;              // [18][BN] (storage type) outgoing populations f*_i, i = 1..18,
+                           // of every interface cell at the end of the last step
     uint8_t *flags;
-    double *m, *phi;
+    double *m;             // [BN] interface mass
+    double *phi_cur;       // [BN] fill level at the start of this step
+    double *phi_next;      // [BN] fill level at the end of this step (the other buffer)
     double *rhoG;          // [BN] gas density at interface cells (sigma != 0), else null
-    double *uif;           // [3][BN] interface velocity from f*(t) for anti-bounce-back
     double *mex;           // [BN] excess mass share of converted cells
     double *normal;        // [3][BN] unit normals on the band (sigma != 0)
     uint32_t *band;        // [ceil(BN/32)] band membership bits (sigma != 0)

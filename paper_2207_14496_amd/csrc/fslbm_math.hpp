@@ -115,13 +115,22 @@ __device__ __forceinline__ void py_gradient(const Geom &g, const Cell &c, F val,
                                             double &gy, double &gz) {
 #pragma clang fp contract(off)
     double ax = 0.0, ay = 0.0, az = 0.0, wx = 0.0, wy = 0.0, wz = 0.0;
-    long long base = (long long)c.b * g.N;
+    const long long base = (long long)c.b * g.N;
+    // all 26 loads first (walls read the cell itself and are masked below)
+    double vp[13], vm[13];
+    bool ok[13];
 #pragma unroll
     for (int k = 0; k < 13; ++k) {
-        long long p = nb_local(g, c.x, c.y, c.z, pyx(k), pyy(k), pyz(k));
-        long long m = nb_local(g, c.x, c.y, c.z, -pyx(k), -pyy(k), -pyz(k));
-        if (p >= 0 && m >= 0) {
-            double dv = val(base + p) - val(base + m);
+        const int p = nb_local(g, c.x, c.y, c.z, pyx(k), pyy(k), pyz(k));
+        const int m = nb_local(g, c.x, c.y, c.z, -pyx(k), -pyy(k), -pyz(k));
+        ok[k] = p >= 0 && m >= 0;
+        vp[k] = val(base + (p >= 0 ? p : c.n));
+        vm[k] = val(base + (m >= 0 ? m : c.n));
+    }
+#pragma unroll
+    for (int k = 0; k < 13; ++k) {
+        if (ok[k]) {
+            const double dv = vp[k] - vm[k];
             if (pyx(k)) { ax += pyw(k) * pyx(k) * dv; wx += 2.0 * pyw(k); }
             if (pyy(k)) { ay += pyw(k) * pyy(k) * dv; wy += 2.0 * pyw(k); }
             if (pyz(k)) { az += pyw(k) * pyz(k) * dv; wz += 2.0 * pyw(k); }

@@ -1,20 +1,28 @@
 // step_kernels.hip -- the kernels of one FSLBM time step on gfx950.
 //
 // Per step (parity p = steps done mod 2; layout A before even steps, B before
-// odd ones, see fslbm_device.hpp):
+// odd ones, see fslbm_device.hpp), four kernels plus three for surface tension:
 //   [sigma != 0]  k_band -> k_normals -> k_curvature    (Sec. 2.2, curvature)
-//   k_mass_exchange     interface list: mass flux, m(t+1), interface velocity
-//   k_stream_collide    every cell: in-place stream + bounce-back + anti-bounce-
-//                       back + fill level + conversion marks + collision
-//   k_resolve           interface list: conflict rules, new/from-liquid lists
-//   k_refill<scheme>    new-interface list: one of the five schemes (Sec. 3.1)
-//   k_apply             conversions, next interface list, excess mass
-//   k_excess_gather     converted list: receiver counts (Sec. 2.2, excess mass)
-//   k_excess_scatter    next interface list: gather shares, reservoir, phi,
-//                       forced filling/emptying classes
+//   k_stream_collide  liquid cells: in-place stream + bounce-back + collide
+//   k_interface       (concurrently, second stream) interface cells: the same
+//                     plus the mass exchange (Sec. 2.2 mass flux with the
+//                     forced filling/emptying table), the anti-bounce-back
+//                     condition, phi = m/rho and the conversion marks
+//   k_resolve         interface list: conflict rules -> new / from-liquid lists
+//   k_convert         new cells: refilling (Sec. 3.1), 32 lanes per cell;
+//                     interface cells: conversions, excess mass and receiver
+//                     counts (Sec. 2.2); the next interface list
+//   k_excess          next interface list: gather excess shares and the
+//                     reservoir, phi, forced classes; bookkeeping for the next step
 // Only the bulk kernel touches every cell; the others walk compacted int32
-// lists with grid-stride loops whose lengths live in device memory, so the
-// whole sequence can be captured once and replayed as a HIP graph.
+// lists whose lengths live in device memory, so the whole sequence can be
+// captured once and replayed as a HIP graph.
+//
+// On MI355X every kernel boundary costs several microseconds (dispatch plus
+// the cross-XCD cache write-back and invalidate), which dominates these short
+// list kernels, so work that can share a kernel does.  Inside the list
+// kernels every load that does not depend on another is issued first, with
+// clamped in-bounds addresses for walls, and only then selected.
 #include "fslbm_kernels.hpp"
 #include "fslbm_math.hpp"
 
@@ -28,29 +36,47 @@ namespace {   // every kernel has internal linkage; only the launchers are expor
                    k##_end = (count) < a.cap ? (long long)(count) : a.cap;             \
          k < k##_end; k += (long long)gridDim.x * blockDim.x)
 
+// The same over [0, count) without clamping, but every lane runs the same
+// number of iterations (lanes past the end see in == false), so wavefront-wide
+// ballots and shuffles inside stay convergent.
+#define FOR_UNIFORM(k, in, count)                                                      \
+    for (long long k##_end = (count), k##_str = (long long)gridDim.x * blockDim.x,     \
+                   k##_it = 0, k##_n = (k##_end + k##_str - 1) / k##_str,              \
+                   k = (long long)blockIdx.x * blockDim.x + threadIdx.x;               \
+         k##_it < k##_n; ++k##_it, k += k##_str)                                       \
+        if (const bool in = k < k##_end; true)
+
+__device__ __forceinline__ long long clamp_cap(const StepArgs &a, int32_t v) {
+    return v < a.cap ? (long long)v : a.cap;
+}
+
 // ------------------------------------------------------------------ helpers
 
-// Shifted PDF at a slot, decoded to double.
+// Shifted PDF at a flat slot index, decoded to double.
 template <int ST>
-__device__ __forceinline__ double load_slot(const StepArgs &a, Slot s) {
+__device__ __forceinline__ double load_slot(const StepArgs &a, long long off) {
     using C = Codec<ST>;
-    const typename C::M *pdf = static_cast<const typename C::M *>(a.pdf);
-    return double(C::load(pdf + slot_index(a.g, s)));
+    return double(C::load(static_cast<const typename C::M *>(a.pdf) + off));
 }
 template <int ST>
-__device__ __forceinline__ void store_slot(const StepArgs &a, Slot s, double v) {
+__device__ __forceinline__ void store_slot(const StepArgs &a, long long off, double v) {
     using C = Codec<ST>;
-    typename C::M *pdf = static_cast<typename C::M *>(a.pdf);
-    C::store(pdf + slot_index(a.g, s), typename C::T(v));
+    C::store(static_cast<typename C::M *>(a.pdf) + off, typename C::T(v));
+}
+// Outgoing-population copy of interface cell gid, direction i in 1..18.
+template <int ST>
+__device__ __forceinline__ void store_fo(const StepArgs &a, int i, long long gid, double v) {
+    using C = Codec<ST>;
+    C::store(static_cast<typename C::M *>(a.fo) + (long long)(i - 1) * a.g.BN + gid,
+             typename C::T(v));
 }
 
 // Shifted post-collision populations of a cell in the given layout.
 template <int ST>
-__device__ __forceinline__ void load_cell(const StepArgs &a, int layoutB, long long gid,
+__device__ __forceinline__ void load_cell(const StepArgs &a, int layoutB, const Cell &c,
                                           double (&d)[Q]) {
-    Cell c = decode(a.g, gid);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) d[i] = load_slot<ST>(a, slot_of(a.g, layoutB, c, gid, i));
+    for (int i = 0; i < Q; ++i) d[i] = load_slot<ST>(a, slot_flat(a.g, layoutB, c, i));
 }
 
 __device__ __forceinline__ int fclass(uint8_t fl) {
@@ -66,42 +92,121 @@ __device__ __forceinline__ double link_flux(int cc, int cn, double fin, double f
     return fin;
 }
 
-// ------------------------------------------------------------------ surface
+// Cell type after this step's conversions, read from a flag byte in either
+// the encoding before k_convert rewrites it or the one after.
+__device__ __forceinline__ uint8_t type_after(uint8_t f) {
+    if (!(f & F_TYPE)) return 0;   // no cell (wall)
+    if (f & F_IF) return (f & F_MARK_A) ? F_LIQ : ((f & F_MARK_B) ? F_GAS : F_IF);
+    if (f & F_GAS) return (f & F_MARK_A) ? F_IF : F_GAS;
+    return (f & F_MARK_B) ? F_IF : F_LIQ;   // liquid (possibly CONV-marked)
+}
 
-// Mark the band (interface cells and their 3x3x3 neighbours) once and list it.
-__global__ void k_band(StepArgs a) {
-    const int32_t nold = a.cnt[C_IF0 + a.parity];
-    FOR_LIST(k, nold) {
-        long long gid = a.list_old[k];
-        Cell c = decode(a.g, gid);
-        long long base = (long long)c.b * a.g.N;
-        for (int dz = -1; dz <= 1; ++dz)
-            for (int dy = -1; dy <= 1; ++dy)
-                for (int dx = -1; dx <= 1; ++dx) {
-                    long long q = nb_local(a.g, c.x, c.y, c.z, dx, dy, dz);
-                    if (q < 0) continue;
-                    long long cell = base + q;
-                    unsigned int bit = 1u << (cell & 31);
-                    unsigned int old = atomicOr(a.band + (cell >> 5), bit);
-                    if (!(old & bit)) {
-                        int32_t pos = atomicAdd(a.cnt + C_BAND, 1);
-                        if (pos < a.cap) a.list_band[pos] = int32_t(cell);
-                        else atomicOr(a.cnt + C_ERR, E_LIST_OVERFLOW);
-                    }
-                }
+// Valid refill source: liquid, or interface that is not emptying (new
+// interface cells are still gas-typed while k_convert runs).  Holds for the
+// flag encodings both before and after k_convert's own rewrites.
+__device__ __forceinline__ bool refill_source(uint8_t f) {
+    return (f & F_LIQ) || ((f & F_IF) && !(f & F_MARK_B));
+}
+
+// Neighbour local indices of cell c along the 18 D3Q19 directions (-1 = wall).
+__device__ __forceinline__ void neighbours(const Geom &g, const Cell &c, int (&nb)[Q]) {
+    nb[0] = c.n;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) nb[i] = nb_local(g, c.x, c.y, c.z, cx(i), cy(i), cz(i));
+}
+
+// Append the entries val(i) of every lane whose bit i is set in sel (i < 32)
+// to list[*count] with one atomic per wavefront.  Must be called by all lanes
+// of the wavefront that are active in the enclosing loop.
+template <int NI, typename V>
+__device__ __forceinline__ void wave_append_sel(uint32_t sel, V val, int32_t *list, int32_t *count,
+                                                long long cap, int32_t *err) {
+    unsigned long long masks[NI];
+    int pre[NI];
+    int tot = 0;
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        masks[i] = __ballot((sel >> i) & 1u);
+        pre[i] = tot;
+        tot += __popcll(masks[i]);
+    }
+    if (tot == 0) return;
+    const unsigned long long active = __ballot(1);
+    const int lane = __lane_id();
+    const int leader = __ffsll((long long)active) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(count, tot);
+    base = __shfl(base, leader);
+    const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        if ((sel >> i) & 1u) {
+            long long pos = (long long)base + pre[i] + __popcll(masks[i] & below);
+            if (pos < cap) list[pos] = val(i);
+            else atomicOr(err, E_LIST_OVERFLOW);
+        }
     }
 }
 
-// Unit normal n^ = grad(phi)/|grad(phi)| on the band (Parker-Youngs).
-__global__ void k_normals(StepArgs a) {
-    const int32_t nb = a.cnt[C_BAND];
+// Sum of v over each aligned group of 32 lanes (every lane gets the sum).
+__device__ __forceinline__ double group32_sum(double v) {
+#pragma unroll
+    for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off, 32);
+    return v;
+}
+__device__ __forceinline__ double group32_max(double v) {
+#pragma unroll
+    for (int off = 16; off > 0; off >>= 1) {
+        double o = __shfl_xor(v, off, 32);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// f_eq_i(rho,u) - w_i for a runtime direction i (one lane per direction).
+__device__ __forceinline__ double feq_shift_rt(int i, double rho, double ux, double uy, double uz) {
+    const double uc = k_cx[i] * ux + k_cy[i] * uy + k_cz[i] * uz;
+    const double uu = ux * ux + uy * uy + uz * uz;
+    const double w = i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+    return w * ((rho - 1.0) + rho * (3.0 * uc + 4.5 * uc * uc - 1.5 * uu));
+}
+
+// ------------------------------------------------------------------ surface
+
+// Mark the band (interface cells and their 3x3x3 neighbours) once and list it.
+__global__ __launch_bounds__(256) void k_band(StepArgs a) {
+    FOR_UNIFORM(k, in, clamp_cap(a, a.cnt[C_IF0 + a.parity])) {
+        uint32_t sel = 0;
+        long long cells[27];
+        if (in) {
+            const long long gid = a.list_old[k];
+            const Cell c = decode(a.g, gid);
+            const long long base = (long long)c.b * a.g.N;
+            unsigned int olds[27], bits[27];
+#pragma unroll
+            for (int j = 0; j < 27; ++j) {
+                const int q = nb_local(a.g, c.x, c.y, c.z, j % 3 - 1, (j / 3) % 3 - 1, j / 9 - 1);
+                cells[j] = base + (q >= 0 ? q : c.n);
+                bits[j] = 1u << (cells[j] & 31);
+                olds[j] = q >= 0 ? atomicOr(a.band + (cells[j] >> 5), bits[j]) : bits[j];
+            }
+#pragma unroll
+            for (int j = 0; j < 27; ++j) sel |= (olds[j] & bits[j]) ? 0u : (1u << j);
+        }
+        wave_append_sel<27>(sel, [&](int j) { return int32_t(cells[j]); }, a.list_band,
+                            a.cnt + C_BAND, a.cap, a.cnt + C_ERR);
+    }
+}
+
+// Unit normal n^ = grad(phi)/|grad(phi)| on the band (Parker-Youngs), phi(t).
+__global__ __launch_bounds__(256) void k_normals(StepArgs a) {
     const long long BN = a.g.BN;
-    FOR_LIST(k, nb) {
-        long long gid = a.list_band[k];
-        Cell c = decode(a.g, gid);
+    FOR_LIST(k, a.cnt[C_BAND]) {
+        const long long gid = a.list_band[k];
+        const Cell c = decode(a.g, gid);
         double gx, gy, gz;
-        py_gradient(a.g, c, [&](long long q) { return a.phi[q]; }, gx, gy, gz);
-        double len = sqrt(gx * gx + gy * gy + gz * gz);
+        py_gradient(a.g, c, [&](long long q) { return a.phi_cur[q]; }, gx, gy, gz);
+        const double len = sqrt(gx * gx + gy * gy + gz * gz);
         a.normal[gid] = len > 0.0 ? gx / len : 0.0;
         a.normal[BN + gid] = len > 0.0 ? gy / len : 0.0;
         a.normal[2 * BN + gid] = len > 0.0 ? gz / len : 0.0;
@@ -110,108 +215,113 @@ __global__ void k_normals(StepArgs a) {
 }
 
 // Mean curvature kappa_m = -div(n^)/2 and gas density rho_G = 3 (p_V + 2 sigma kappa_m).
-__global__ void k_curvature(StepArgs a) {
-    const int32_t nold = a.cnt[C_IF0 + a.parity];
+__global__ __launch_bounds__(256) void k_curvature(StepArgs a) {
     const long long BN = a.g.BN;
-    FOR_LIST(k, nold) {
-        long long gid = a.list_old[k];
-        Cell c = decode(a.g, gid);
+    FOR_LIST(k, a.cnt[C_IF0 + a.parity]) {
+        const long long gid = a.list_old[k];
+        const Cell c = decode(a.g, gid);
         double d0, d1, d2, t;
         py_gradient(a.g, c, [&](long long q) { return a.normal[q]; }, d0, t, t);
         py_gradient(a.g, c, [&](long long q) { return a.normal[BN + q]; }, t, d1, t);
         py_gradient(a.g, c, [&](long long q) { return a.normal[2 * BN + q]; }, t, t, d2);
-        double km = -0.5 * ((d0 + d1) + d2);
+        const double km = -0.5 * ((d0 + d1) + d2);
         a.rhoG[gid] = 3.0 * (a.p_volume + 2.0 * a.sigma * km);
-    }
-}
-
-// ------------------------------------------------------------------ mass exchange
-
-// Interface mass exchange over the current interface list (Sec. 2.2 mass flux
-// with the forced filling/emptying table), plus the velocity of each interface
-// cell from its stored post-collision populations for the anti-bounce-back
-// condition.  Block 0 also resets this step's list counters and carries the
-// reservoir over; a second loop clears the previous step's conversion marks.
-template <int ST>
-__global__ void k_mass_exchange(StepArgs a) {
-    const int p = a.parity;
-    if (blockIdx.x == 0) {
-        for (int b = threadIdx.x; b < a.B; b += blockDim.x) {
-            // mass that found no receiver is kept while the domain has no interface
-            double carry = a.nif_dom[(1 - p) * a.B + b] > 0 ? 0.0 : a.res[(1 - p) * a.B + b];
-            a.res[p * a.B + b] = carry;
-            a.nif_dom[p * a.B + b] = 0;
-        }
-        if (threadIdx.x == 0) {
-            a.cnt[C_IF0 + (1 - p)] = 0;
-            a.cnt[C_NEWG] = 0;
-            a.cnt[C_FROML] = 0;
-            a.cnt[C_CONV0 + p] = 0;
-        }
-    }
-    const int layoutB = p;   // layout before this step
-    const int32_t nold = a.cnt[C_IF0 + p];
-    const long long BN = a.g.BN;
-    FOR_LIST(k, nold) {
-        long long gid = a.list_old[k];
-        Cell c = decode(a.g, gid);
-        uint8_t fl = a.flags[gid];
-        int cc = fclass(fl);
-        double phx = a.phi[gid];
-        double dm = 0.0;
-#pragma unroll
-        for (int i = 1; i < Q; ++i) {
-            long long nbg = nb_dir(a.g, c, i);
-            if (nbg < 0) continue;
-            uint8_t fn = a.flags[nbg];
-            if (fn & F_GAS) continue;
-            // the two populations crossing the link x <-> x + c_i, unshifted: the
-            // one-sided fluxes of the forced classes need absolute values
-            Slot sin_ = layoutB ? Slot{opp(i), gid} : Slot{i, nbg};   // f*_opp(i)(x + c_i)
-            Slot sout = layoutB ? Slot{i, nbg} : Slot{opp(i), gid};   // f*_i(x)
-            const double w = wgt<double>(i);
-            double fin = w + load_slot<ST>(a, sin_), fout = w + load_slot<ST>(a, sout);
-            if (fn & F_LIQ) dm += fin - fout;
-            else dm += 0.5 * (phx + a.phi[nbg]) * link_flux(cc, fclass(fn), fin, fout);
-        }
-        a.m[gid] = a.m[gid] + dm;
-        double d[Q];
-        load_cell<ST>(a, layoutB, gid, d);
-        const double *gr = a.grav + 3 * c.b;
-        double rho, ux, uy, uz;
-        moments_post(d, gr[0], gr[1], gr[2], rho, ux, uy, uz);
-        a.uif[gid] = ux;
-        a.uif[BN + gid] = uy;
-        a.uif[2 * BN + gid] = uz;
-    }
-    const int32_t nconv = a.cnt[C_CONV0 + (1 - p)];
-    FOR_LIST(k, nconv) {
-        long long gid = a.list_conv_prev[k];
-        a.flags[gid] = uint8_t(a.flags[gid] & ~F_CONV);
     }
 }
 
 // ------------------------------------------------------------------ bulk
 
-// Fused stream + boundary conditions + collision for every cell (Sec. 2.1,
-// 2.2).  PAR = 0: layout A -> B (pull from neighbours' slots, push into
-// neighbours' slots); PAR = 1: layout B -> A (local slots only).  Gas cells
-// exit after the flag read.  Interface cells additionally rebuild PDFs
-// arriving from gas with the anti-bounce-back condition, update their fill
-// level phi = m/rho and mark fill levels beyond the conversion thresholds.
-template <int ST, int COLL, int PAR>
-__global__ __launch_bounds__(256) void k_stream_collide(StepArgs a) {
+// Interface part of the update of cell gid (Sec. 2.2): mass exchange over the
+// 18 links with the populations that just streamed in (d, before any
+// reconstruction) and the cell's own outgoing populations of the last step
+// (fo buffer); anti-bounce-back for populations arriving from gas, with the
+// cell's velocity of the last step; phi = m/rho; conversion marks.
+template <int ST, int PAR>
+__device__ __forceinline__ void interface_part(const StepArgs &a, const long long gid, const uint8_t fl,
+                                               const Cell &c, const int (&src)[Q],
+                                               typename Codec<ST>::T (&d)[Q]) {
+    using C = Codec<ST>;
+    using T = typename C::T;
+    const long long BN = a.g.BN, N = a.g.N;
+    const long long cbase = (long long)c.b * N;
+    const typename C::M *fob = static_cast<const typename C::M *>(a.fo);
+    // own outgoing populations f*_i(x, t), i = 1..18, and neighbour flags
+    T fo[Q];
+    uint8_t fn[Q];   // flag of the cell x - c_i (source of direction i)
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        fo[i] = C::load(fob + (long long)(i - 1) * BN + gid);
+        fn[i] = src[i] >= 0 ? a.flags[cbase + src[i]] : uint8_t(0);
+    }
+    const double m0 = a.m[gid];
+    const double phx = a.phi_cur[gid];
+    // mass exchange: the neighbour x + c_i is the source of direction opp(i)
+    const int cc = fclass(fl);
+    double dm = 0.0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const int o = opp(i);
+        const uint8_t f = fn[o];
+        if (src[o] < 0 || (f & F_GAS)) continue;
+        const double w = wgt<double>(i);
+        const double fin = w + double(d[o]);    // f*_opp(i)(x + c_i, t)
+        const double fout = w + double(fo[i]);  // f*_i(x, t)
+        if (f & F_LIQ) {
+            dm += fin - fout;
+        } else {
+            const double phn = a.phi_cur[cbase + src[o]];
+            dm += 0.5 * (phx + phn) * link_flux(cc, fclass(f), fin, fout);
+        }
+    }
+    // velocity of the cell at the last step from its post-collision populations
+    double r0 = 1.0 + double(d[0]), jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const double v = double(fo[i]);
+        r0 += v;
+        if (cx(i)) jx += cx(i) * v;
+        if (cy(i)) jy += cy(i) * v;
+        if (cz(i)) jz += cz(i) * v;
+    }
+    const double *gr = a.grav + 3 * c.b;
+    const double ux = jx / r0 - 0.5 * gr[0], uy = jy / r0 - 0.5 * gr[1], uz = jz / r0 - 0.5 * gr[2];
+    const double rg = a.rhoG ? a.rhoG[gid] : 3.0 * a.p_volume;
+    const double uu = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        if (src[i] >= 0 && (fn[i] & F_GAS)) {
+            // anti-bounce-back: f_i = f_eq_i + f_eq_opp(i) - f*_opp(i)(x)
+            const double uc = cx(i) * ux + cy(i) * uy + cz(i) * uz;
+            const double w = wgt<double>(i);
+            const double e2 = 2.0 * w * rg * (1.0 + 4.5 * uc * uc - 1.5 * uu);
+            d[i] = T(e2 - 2.0 * w - double(fo[opp(i)]));
+        }
+    }
+    const double m1 = m0 + dm;
+    double drho = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) drho += double(d[i]);
+    const double ph = m1 / (1.0 + drho);
+    a.m[gid] = m1;
+    a.phi_next[gid] = ph;
+    const uint8_t mark = ph > 1.0 + a.eps_phi ? F_MARK_A : (ph < -a.eps_phi ? F_MARK_B : 0);
+    if (mark) a.flags[gid] = uint8_t(fl | mark);
+}
+
+// Fused stream + boundary conditions + collision of one liquid (IF = false) or
+// interface (IF = true) cell (Sec. 2.1, 2.2).  PAR = 0: layout A -> B (pull
+// from neighbours' slots, push into neighbours' slots); PAR = 1: layout B -> A
+// (local slots only).  Every cell reads and writes only its own slot set, so
+// cells may be updated in any order and by different kernels.
+template <int ST, int COLL, int PAR, bool IF>
+__device__ __forceinline__ void update_cell(const StepArgs &a, const long long gid, const uint8_t fl) {
     using C = Codec<ST>;
     using T = typename C::T;
     using Mem = typename C::M;
-    const Geom g = a.g;
-    const long long gid = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (gid >= g.BN) return;
-    const uint8_t fl = a.flags[gid];
-    if (!(fl & (F_LIQ | F_IF))) return;
+    const Geom &g = a.g;
     const Cell c = decode(g, gid);
     Mem *base = static_cast<Mem *>(a.pdf) + (long long)c.b * Q * g.N;
-    const long long n = c.n;
+    const int n = c.n;
     const long long N = g.N;
 
     // neighbour coordinates per axis (-1 = wall)
@@ -223,52 +333,30 @@ __global__ __launch_bounds__(256) void k_stream_collide(StepArgs a) {
     ys[2] = c.y < g.ny - 1 ? c.y + 1 : (g.per[1] ? 0 : -1);
     zs[0] = c.z > 0 ? c.z - 1 : (g.per[2] ? g.nz - 1 : -1);
     zs[2] = c.z < g.nz - 1 ? c.z + 1 : (g.per[2] ? 0 : -1);
-    auto nbl = [&](int dx, int dy, int dz) -> long long {
+    auto nbl = [&](int dx, int dy, int dz) -> int {
         int X = xs[dx + 1], Y = ys[dy + 1], Z = zs[dz + 1];
         if (X < 0 || Y < 0 || Z < 0) return -1;
-        return ((long long)Z * g.ny + Y) * g.nx + X;
+        return (Z * g.ny + Y) * g.nx + X;
     };
+    int src[Q];   // source cell x - c_i of each incoming population (-1 = wall)
+    src[0] = n;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) src[i] = nbl(-cx(i), -cy(i), -cz(i));
 
     T d[Q];
     d[0] = C::load(base + n);
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
         if (PAR == 0) {
-            long long s = nbl(-cx(i), -cy(i), -cz(i));
             // wall: the redirected f*_opp(i)(x) sits in (i, x)
-            d[i] = s < 0 ? C::load(base + i * N + n) : C::load(base + opp(i) * N + s);
+            const uint32_t off = src[i] < 0 ? uint32_t(i * N + n) : uint32_t(opp(i) * N + src[i]);
+            d[i] = C::load(base + off);
         } else {
             d[i] = C::load(base + i * N + n);
         }
     }
 
-    if (fl & F_IF) {
-        const long long BN = g.BN;
-        const double ux = a.uif[gid], uy = a.uif[BN + gid], uz = a.uif[2 * BN + gid];
-        const double rg = a.rhoG ? a.rhoG[gid] : 3.0 * a.p_volume;
-        const double uu = ux * ux + uy * uy + uz * uz;
-        const uint8_t *fb = a.flags + (long long)c.b * N;
-#pragma unroll
-        for (int i = 1; i < Q; ++i) {
-            long long s = nbl(-cx(i), -cy(i), -cz(i));
-            if (s >= 0 && (fb[s] & F_GAS)) {
-                // anti-bounce-back: f_i = f_eq_i + f_eq_opp(i) - f*_opp(i)(x)
-                double fo = PAR == 0 ? double(C::load(base + i * N + n))
-                                     : double(C::load(base + opp(i) * N + s));
-                double uc = cx(i) * ux + cy(i) * uy + cz(i) * uz;
-                double w = wgt<double>(i);
-                double e2 = 2.0 * w * rg * (1.0 + 4.5 * uc * uc - 1.5 * uu);
-                d[i] = T(e2 - 2.0 * w - fo);
-            }
-        }
-        double drho = 0.0;
-#pragma unroll
-        for (int i = 0; i < Q; ++i) drho += double(d[i]);
-        const double ph = a.m[gid] / (1.0 + drho);
-        a.phi[gid] = ph;
-        uint8_t mark = ph > 1.0 + a.eps_phi ? F_MARK_A : (ph < -a.eps_phi ? F_MARK_B : 0);
-        if (mark) a.flags[gid] = uint8_t(fl | mark);
-    }
+    if (IF) interface_part<ST, PAR>(a, gid, fl, c, src, d);
 
     const double *gr = a.grav + 3 * c.b;
     const T om = T(a.omega[c.b]);
@@ -283,12 +371,48 @@ __global__ __launch_bounds__(256) void k_stream_collide(StepArgs a) {
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
         if (PAR == 0) {
-            long long t = nbl(cx(i), cy(i), cz(i));
-            if (t < 0) C::store(base + opp(i) * N + n, d[i]);   // bounce-back at write
-            else C::store(base + i * N + t, d[i]);
+            int t = nbl(cx(i), cy(i), cz(i));
+            // a wall neighbour gets the bounce-back slot (opp(i), x) instead
+            const uint32_t off = t < 0 ? uint32_t(opp(i) * N + n) : uint32_t(i * N + t);
+            C::store(base + off, d[i]);
         } else {
             C::store(base + opp(i) * N + n, d[i]);
         }
+    }
+    if (IF) {
+        typename C::M *fob = static_cast<typename C::M *>(a.fo);
+#pragma unroll
+        for (int i = 1; i < Q; ++i) C::store(fob + (long long)(i - 1) * g.BN + gid, d[i]);
+    }
+}
+
+// Bulk kernel over the liquid cells: one thread per cell, one workgroup per
+// 256 consecutive cells (x fastest, so every PDF access of a wavefront is a
+// contiguous row segment).  Gas and interface cells cost one flag-byte read;
+// interface cells are updated by k_interface, which runs concurrently.
+template <int ST, int COLL, int PAR>
+__global__ __launch_bounds__(256) void k_stream_collide(StepArgs a) {
+    const long long gid = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (gid == 0) {
+        // this step's conversion lists start empty (the last step's lengths
+        // stayed readable until now)
+        a.cnt[C_NEWG] = 0;
+        a.cnt[C_FROML] = 0;
+        a.cnt[C_CONV0 + a.parity] = 0;
+    }
+    if (gid >= a.g.BN) return;
+    const uint8_t fl = a.flags[gid];
+    if (fl & F_LIQ) update_cell<ST, COLL, PAR, false>(a, gid, fl);
+}
+
+// Interface cells of the list: the same update plus mass exchange,
+// anti-bounce-back, fill level and conversion marks.  Latency-bound and small,
+// it runs on a second stream beside the bandwidth-bound bulk kernel.
+template <int ST, int COLL, int PAR>
+__global__ __launch_bounds__(256) void k_interface(StepArgs a) {
+    FOR_LIST(k, a.cnt[C_IF0 + a.parity]) {
+        const long long gid = a.list_old[k];
+        update_cell<ST, COLL, PAR, true>(a, gid, a.flags[gid]);
     }
 }
 
@@ -298,261 +422,264 @@ __global__ __launch_bounds__(256) void k_stream_collide(StepArgs a) {
 // 1+eps becomes a new interface cell; a cell emptying under -eps next to a
 // filling cell stays interface; liquid next to a remaining emptying cell
 // becomes interface.  Each rule reads only the fill marks, so one pass does all.
-__global__ void k_resolve(StepArgs a) {
-    const int32_t nold = a.cnt[C_IF0 + a.parity];
-    FOR_LIST(k, nold) {
-        long long gid = a.list_old[k];
-        Cell c = decode(a.g, gid);
-        uint8_t fl = a.flags[gid];
-        if (fl & F_MARK_A) {
+// A second loop clears the marks of the cells converted in the last step.
+__global__ __launch_bounds__(256) void k_resolve(StepArgs a) {
+    const long long N = a.g.N;
+    FOR_UNIFORM(k, in, clamp_cap(a, a.cnt[C_IF0 + a.parity])) {
+        uint32_t sel_g = 0, sel_l = 0;
+        long long cbase = 0;
+        int nb[Q];
+        if (in) {
+            const long long gid = a.list_old[k];
+            const Cell c = decode(a.g, gid);
+            cbase = (long long)c.b * N;
+            neighbours(a.g, c, nb);
+            const uint8_t fl = a.flags[gid];
+            uint8_t fn[Q];
 #pragma unroll
-            for (int i = 1; i < Q; ++i) {
-                long long q = nb_dir(a.g, c, i);
-                bool add = false;
-                if (q >= 0 && (a.flags[q] & F_GAS)) add = !(flag_or(a.flags, q, F_MARK_A) & F_MARK_A);
-                wave_append(add, int32_t(q), a.list_newg, a.cnt + C_NEWG, a.cap, a.cnt + C_ERR);
-            }
-        } else if (fl & F_MARK_B) {
-            bool near_fill = false;
+            for (int i = 1; i < Q; ++i) fn[i] = a.flags[cbase + (nb[i] >= 0 ? nb[i] : c.n)];
+            if (fl & F_MARK_A) {
+                uint8_t old[Q];
 #pragma unroll
-            for (int i = 1; i < Q; ++i) {
-                long long q = nb_dir(a.g, c, i);
-                if (q >= 0) {
-                    uint8_t fq = a.flags[q];
-                    near_fill |= (fq & F_IF) && (fq & F_MARK_A);
-                }
-            }
-            if (near_fill) {
-                flag_clear(a.flags, gid, F_MARK_B);
-            } else {
+                for (int i = 1; i < Q; ++i)
+                    old[i] = (nb[i] >= 0 && (fn[i] & F_GAS)) ? flag_or(a.flags, cbase + nb[i], F_MARK_A)
+                                                            : F_MARK_A;
 #pragma unroll
-                for (int i = 1; i < Q; ++i) {
-                    long long q = nb_dir(a.g, c, i);
-                    bool add = false;
-                    if (q >= 0 && (a.flags[q] & F_LIQ))
-                        add = !(flag_or(a.flags, q, F_MARK_B) & F_MARK_B);
-                    wave_append(add, int32_t(q), a.list_froml, a.cnt + C_FROML, a.cap,
-                                a.cnt + C_ERR);
+                for (int i = 1; i < Q; ++i) sel_g |= (old[i] & F_MARK_A) ? 0u : (1u << i);
+            } else if (fl & F_MARK_B) {
+                bool near_fill = false;
+#pragma unroll
+                for (int i = 1; i < Q; ++i)
+                    near_fill |= nb[i] >= 0 && (fn[i] & F_IF) && (fn[i] & F_MARK_A);
+                if (near_fill) {
+                    flag_clear(a.flags, gid, F_MARK_B);
+                } else {
+                    uint8_t old[Q];
+#pragma unroll
+                    for (int i = 1; i < Q; ++i)
+                        old[i] = (nb[i] >= 0 && (fn[i] & F_LIQ)) ? flag_or(a.flags, cbase + nb[i], F_MARK_B)
+                                                                : F_MARK_B;
+#pragma unroll
+                    for (int i = 1; i < Q; ++i) sel_l |= (old[i] & F_MARK_B) ? 0u : (1u << i);
                 }
             }
         }
+        wave_append_sel<Q>(sel_g, [&](int i) { return int32_t(cbase + nb[i]); }, a.list_newg,
+                           a.cnt + C_NEWG, a.cap, a.cnt + C_ERR);
+        wave_append_sel<Q>(sel_l, [&](int i) { return int32_t(cbase + nb[i]); }, a.list_froml,
+                           a.cnt + C_FROML, a.cap, a.cnt + C_ERR);
+    }
+    FOR_LIST(k, a.cnt[C_CONV0 + (1 - a.parity)]) {
+        const long long gid = a.list_conv_prev[k];
+        flag_clear(a.flags, gid, F_CONV);
     }
 }
 
-// Valid refill source: liquid, or interface that is not emptying (new
-// interface cells are still gas-typed at this point).
-__device__ __forceinline__ bool refill_source(uint8_t f) {
-    return (f & F_LIQ) || ((f & F_IF) && !(f & F_MARK_B));
-}
-
-// Refill every new interface cell (Sec. 3.1) and write its populations into
-// the slots of the layout after this step.
+// Refilling of one new interface cell x by 32 cooperating lanes (Sec. 3.1).
+// Lane j in 1..18 loads neighbour x + c_j; lane i in 0..18 produces f_i.
+// Returns nothing; writes the populations in the layout after this step and
+// the cell's outgoing copy, and sets m = 0.
 template <int ST, int SCHEME>
-__global__ void k_refill(StepArgs a) {
-    const int32_t nn = a.cnt[C_NEWG];
+__device__ __forceinline__ void refill_group(const StepArgs &a, const long long gid, const int lane,
+                                             const bool active) {
     const int layoutB = 1 - a.parity;   // layout after this step
-    FOR_LIST(k, nn) {
-        long long gid = a.list_newg[k];
-        Cell c = decode(a.g, gid);
-        const double *gr = a.grav + 3 * c.b;
-        bool val[Q];
-        int nv = 0;
-        double rs = 0.0, usx = 0.0, usy = 0.0, usz = 0.0;
-        // face neighbours' velocities for GEQ
-        double fu[7][3];
-        double avg[Q];
-#pragma unroll
-        for (int i = 0; i < Q; ++i) avg[i] = 0.0;
-        val[0] = false;
-#pragma unroll
-        for (int i = 1; i < Q; ++i) {
-            long long q = nb_dir(a.g, c, i);
-            val[i] = q >= 0 && refill_source(a.flags[q]);
-            if (val[i]) {
-                ++nv;
-                double d[Q];
-                load_cell<ST>(a, layoutB, q, d);
-                double r, ux, uy, uz;
-                moments_post(d, gr[0], gr[1], gr[2], r, ux, uy, uz);
-                rs += r; usx += ux; usy += uy; usz += uz;
-                if (i <= 6) { fu[i][0] = ux; fu[i][1] = uy; fu[i][2] = uz; }
-                if (SCHEME == 4) {
-#pragma unroll
-                    for (int j = 0; j < Q; ++j) avg[j] += d[j];
-                }
-            }
-        }
-        double out[Q];
-        double rb = 1.0, ub[3] = {0.0, 0.0, 0.0};
-        if (nv > 0) {
-            rb = rs / nv;
-            ub[0] = usx / nv; ub[1] = usy / nv; ub[2] = usz / nv;
-        }
-        {
-            double uu = ub[0] * ub[0] + ub[1] * ub[1] + ub[2] * ub[2];
-#pragma unroll
-            for (int i = 0; i < Q; ++i)
-                out[i] = feq_shift<double>(i, rb, rb - 1.0, ub[0], ub[1], ub[2], uu);
-        }
-        int cn = -1;
-        if ((SCHEME == 1 || SCHEME == 3) && nv > 0) {
-            double nx_, ny_, nz_;
-            py_gradient(a.g, c, [&](long long q) { return a.phi[q]; }, nx_, ny_, nz_);
-            double sc[Q], best = -1e300;
-#pragma unroll
-            for (int i = 1; i < Q; ++i) {
-                sc[i] = val[i] ? __dadd_rn(__dadd_rn(__dmul_rn(double(cx(i)), nx_),
-                                                     __dmul_rn(double(cy(i)), ny_)),
-                                           __dmul_rn(double(cz(i)), nz_))
-                               : -1e300;
-                best = sc[i] > best ? sc[i] : best;
-            }
-            double tol = 1e-12 * (fabs(nx_) + fabs(ny_) + fabs(nz_));
-#pragma unroll
-            for (int i = Q - 1; i >= 1; --i)
-                if (val[i] && sc[i] >= best - tol) cn = i;
-        }
-        // offsets of c^n and the first cell along it
-        int ddx = 0, ddy = 0, ddz = 0;
-#pragma unroll
-        for (int i = 1; i < Q; ++i)
-            if (i == cn) { ddx = cx(i); ddy = cy(i); ddz = cz(i); }
-        long long k1 = -1;
-        if (cn > 0) k1 = (long long)c.b * a.g.N + nb_local(a.g, c.x, c.y, c.z, ddx, ddy, ddz);
+    const long long N = a.g.N;
+    const Cell c = decode(a.g, gid);
+    const long long cbase = (long long)c.b * N;
+    const double *gr = a.grav + 3 * c.b;
+    const int j = lane;
+    const bool has = active && j >= 1 && j < Q;
+    const int ox = has ? k_cx[j] : 0, oy = has ? k_cy[j] : 0, oz = has ? k_cz[j] : 0;
+    const int q = has ? nb_local(a.g, c.x, c.y, c.z, ox, oy, oz) : -1;
+    const bool valid = q >= 0 && refill_source(a.flags[cbase + q]);
+    const Cell cq = decode(a.g, cbase + (valid ? q : c.n));
+    double d[Q];
+    load_cell<ST>(a, layoutB, cq, d);
+    double r, ux, uy, uz;
+    moments_post(d, gr[0], gr[1], gr[2], r, ux, uy, uz);
+    const double vw = valid ? 1.0 : 0.0;
+    const double nv = group32_sum(vw);
+    const double rs = group32_sum(vw * r);
+    const double usx = group32_sum(vw * ux), usy = group32_sum(vw * uy), usz = group32_sum(vw * uz);
+    double rb = 1.0, ubx = 0.0, uby = 0.0, ubz = 0.0;
+    if (nv > 0.0) {
+        rb = rs / nv;
+        ubx = usx / nv; uby = usy / nv; ubz = usz / nv;
+    }
+    const int i = lane < Q ? lane : 0;   // output direction of this lane
+    double out = feq_shift_rt(i, rb, ubx, uby, ubz);   // EQ
+
+    if (SCHEME == 1 || SCHEME == 3) {
+        // c^n: the valid direction best aligned with grad(phi) after streaming;
+        // scores within rounding of the best tie and the lowest index wins
+        double nx_ = 0.0, ny_ = 0.0, nz_ = 0.0;
+        if (active)
+            py_gradient(a.g, c, [&](long long k) { return a.phi_next[k]; }, nx_, ny_, nz_);
+        const double sc = valid ? __dadd_rn(__dadd_rn(__dmul_rn(double(ox), nx_), __dmul_rn(double(oy), ny_)),
+                                            __dmul_rn(double(oz), nz_))
+                                : -1e300;
+        const double best = group32_max(sc);
+        const double tol = 1e-12 * (fabs(nx_) + fabs(ny_) + fabs(nz_));
+        const unsigned long long cand = __ballot(valid && sc >= best - tol);
+        const int gbase = __lane_id() & 32;
+        const unsigned int gcand = unsigned((cand >> gbase) & 0xffffffffull);
+        const int cn = gcand ? __ffs(gcand) - 1 : -1;   // lane index = direction
         if (SCHEME == 1 && cn > 0) {
-            // EQ+NEQ: add the non-equilibrium part of the neighbour along c^n
-            double d[Q];
-            load_cell<ST>(a, layoutB, k1, d);
-            double r, ux, uy, uz;
-            moments_post(d, gr[0], gr[1], gr[2], r, ux, uy, uz);
-            double uu = ux * ux + uy * uy + uz * uz;
+            // EQ+NEQ: add the non-equilibrium part of the neighbour along c^n,
+            // f*_i(y) - f_eq_i(rho(y), u(y)), y = x + c^n
+            const int src = gbase + cn;
+            const double rn = __shfl(r, src), uxn = __shfl(ux, src), uyn = __shfl(uy, src),
+                         uzn = __shfl(uz, src);
+            double mine = 0.0;
 #pragma unroll
-            for (int i = 0; i < Q; ++i) out[i] += d[i] - feq_shift<double>(i, r, r - 1.0, ux, uy, uz, uu);
-        } else if (SCHEME == 2 && nv > 0) {
-            // GEQ: Grad's approximation from finite-difference velocity gradients
-            double du[3][3];   // du[al][be] = d u_al / d x_be
-#pragma unroll
-            for (int be = 0; be < 3; ++be) {
-                const int ip = 1 + 2 * be, im = 2 + 2 * be;
-#pragma unroll
-                for (int al = 0; al < 3; ++al) {
-                    if (val[ip] && val[im]) du[al][be] = (fu[ip][al] - fu[im][al]) / 2.0;
-                    else if (val[ip]) du[al][be] = fu[ip][al] - ub[al];
-                    else if (val[im]) du[al][be] = ub[al] - fu[im][al];
-                    else du[al][be] = 0.0;
-                }
+            for (int k = 0; k < Q; ++k) {
+                const double v = __shfl(d[k], src);
+                if (k == i) mine = v;
             }
-            const double tau = 1.0 / a.omega[c.b];
-            const double cs2 = 1.0 / 3.0;
-#pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                const int ci[3] = {cx(i), cy(i), cz(i)};
-                double s = 0.0;
-#pragma unroll
-                for (int al = 0; al < 3; ++al)
-#pragma unroll
-                    for (int be = 0; be < 3; ++be)
-                        s += (du[al][be] + du[be][al]) *
-                             (cs2 * (al == be ? 1.0 : 0.0) - double(ci[al] * ci[be]));
-                out[i] += wgt<double>(i) * rb * tau / (2.0 * cs2) * s;
-            }
+            out += mine - feq_shift_rt(i, rn, uxn, uyn, uzn);
         } else if (SCHEME == 3 && cn > 0) {
             // EXT: extrapolation along c^n, order limited by the run of valid cells
-            Cell c1 = decode(a.g, k1);
-            long long k2 = -1, k3 = -1;
-            long long q2 = nb_local(a.g, c1.x, c1.y, c1.z, ddx, ddy, ddz);
-            if (q2 >= 0) q2 += (long long)c.b * a.g.N;
-            if (q2 >= 0 && refill_source(a.flags[q2])) {
-                k2 = q2;
-                Cell c2 = decode(a.g, k2);
-                long long q3 = nb_local(a.g, c2.x, c2.y, c2.z, ddx, ddy, ddz);
-                if (q3 >= 0) q3 += (long long)c.b * a.g.N;
-                if (q3 >= 0 && refill_source(a.flags[q3])) k3 = q3;
-            }
-            double d1[Q], d2[Q];
-            load_cell<ST>(a, layoutB, k1, d1);
-            if (k2 >= 0) load_cell<ST>(a, layoutB, k2, d2);
-            if (k3 >= 0) {
-                double d3[Q];
-                load_cell<ST>(a, layoutB, k3, d3);
-#pragma unroll
-                for (int i = 0; i < Q; ++i) out[i] = 3.0 * d1[i] - 3.0 * d2[i] + d3[i];
-            } else if (k2 >= 0) {
-#pragma unroll
-                for (int i = 0; i < Q; ++i) out[i] = 2.0 * d1[i] - d2[i];
-            } else {
-#pragma unroll
-                for (int i = 0; i < Q; ++i) out[i] = d1[i];
-            }
-        } else if (SCHEME == 4 && nv > 0) {
-#pragma unroll
-            for (int i = 0; i < Q; ++i) out[i] = avg[i] / nv;
+            const int ddx = k_cx[cn], ddy = k_cy[cn], ddz = k_cz[cn];
+            const int k1 = nb_local(a.g, c.x, c.y, c.z, ddx, ddy, ddz);
+            const Cell c1 = decode(a.g, cbase + k1);
+            const int k2 = nb_local(a.g, c1.x, c1.y, c1.z, ddx, ddy, ddz);
+            const bool v2 = k2 >= 0 && refill_source(a.flags[cbase + k2]);
+            const Cell c2 = decode(a.g, cbase + (v2 ? k2 : k1));
+            const int k3 = v2 ? nb_local(a.g, c2.x, c2.y, c2.z, ddx, ddy, ddz) : -1;
+            const bool v3 = k3 >= 0 && refill_source(a.flags[cbase + k3]);
+            const Cell c3 = decode(a.g, cbase + (v3 ? k3 : k1));
+            const double f1 = load_slot<ST>(a, slot_flat_rt(a.g, layoutB, c1, i));
+            const double f2 = load_slot<ST>(a, slot_flat_rt(a.g, layoutB, c2, i));
+            const double f3 = load_slot<ST>(a, slot_flat_rt(a.g, layoutB, c3, i));
+            out = (v2 && v3) ? 3.0 * f1 - 3.0 * f2 + f3 : (v2 ? 2.0 * f1 - f2 : f1);
         }
+    } else if (SCHEME == 2) {
+        // GEQ: Grad's approximation from finite-difference velocity gradients
+        // (central if both face neighbours are valid, else one-sided with u(x) = u_bar)
+        const int gb = __lane_id() & 32;
+        double fu[7][3];
+        bool fv[7];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) store_slot<ST>(a, slot_of(a.g, layoutB, c, gid, i), out[i]);
-        a.m[gid] = 0.0;
-        a.phi[gid] = 0.0;
+        for (int f = 1; f <= 6; ++f) {
+            fu[f][0] = __shfl(ux, gb + f);
+            fu[f][1] = __shfl(uy, gb + f);
+            fu[f][2] = __shfl(uz, gb + f);
+            fv[f] = __shfl(vw, gb + f) > 0.0;
+        }
+        const double ub[3] = {ubx, uby, ubz};
+        double du[3][3];
+#pragma unroll
+        for (int be = 0; be < 3; ++be) {
+            const int ip = 1 + 2 * be, im = 2 + 2 * be;
+#pragma unroll
+            for (int al = 0; al < 3; ++al) {
+                if (fv[ip] && fv[im]) du[al][be] = (fu[ip][al] - fu[im][al]) / 2.0;
+                else if (fv[ip]) du[al][be] = fu[ip][al] - ub[al];
+                else if (fv[im]) du[al][be] = ub[al] - fu[im][al];
+                else du[al][be] = 0.0;
+            }
+        }
+        const double tau = 1.0 / a.omega[c.b];
+        const double cs2 = 1.0 / 3.0;
+        const int ci[3] = {k_cx[i], k_cy[i], k_cz[i]};
+        double s = 0.0;
+#pragma unroll
+        for (int al = 0; al < 3; ++al)
+#pragma unroll
+            for (int be = 0; be < 3; ++be)
+                s += (du[al][be] + du[be][al]) * (cs2 * (al == be ? 1.0 : 0.0) - double(ci[al] * ci[be]));
+        const double w = i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+        out += w * rb * tau / (2.0 * cs2) * s;
+    } else if (SCHEME == 4) {
+        // AVG: mean of the valid neighbours' populations, direction by direction
+        double mine = 0.0;
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+            const double sk = group32_sum(vw * d[k]);
+            if (k == i) mine = sk;
+        }
+        if (nv > 0.0) out = mine / nv;
+    }
+    if (active && lane < Q) {
+        store_slot<ST>(a, slot_flat_rt(a.g, layoutB, c, i), out);
+        if (i > 0) store_fo<ST>(a, i, gid, out);
+        if (lane == 0) a.m[gid] = 0.0;
     }
 }
 
-// Density sum_i f*_i of a cell in the layout after this step.
+// Density sum_i f*_i of a cell in the layout after this step, also returned
+// as shifted populations.
 template <int ST>
-__device__ __forceinline__ double rho_after(const StepArgs &a, long long gid) {
-    double d[Q];
-    load_cell<ST>(a, 1 - a.parity, gid, d);
+__device__ __forceinline__ double rho_after(const StepArgs &a, const Cell &c, double (&d)[Q]) {
+    load_cell<ST>(a, 1 - a.parity, c, d);
     double s = 0.0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) s += d[i];
     return 1.0 + s;
 }
 
-// Apply the conversions (Sec. 2.2): filled cells become liquid and emptied
-// cells gas (their excess mass is kept in mex), new and from-liquid cells
-// become interface; the next interface list is built on the way.
-template <int ST>
-__global__ void k_apply(StepArgs a) {
+// Conversions (Sec. 2.2, 3.1).  Work items: first every new interface cell
+// (refilled by a group of 32 lanes), then every interface cell of the list
+// (filled cells become liquid, emptied cells gas; their excess mass is split
+// over the receivers, or sent to the reservoir), then every from-liquid cell
+// (mass = its density).  The next interface list is built on the way.  The
+// new cells keep their gas-typed flag until k_excess, so the refill sources
+// read the same validity throughout.
+template <int ST, int SCHEME>
+__global__ __launch_bounds__(256) void k_convert(StepArgs a) {
     const int p = a.parity;
-    auto clamp = [&](int32_t v) { return v < a.cap ? v : int32_t(a.cap); };
-    const int32_t nold = clamp(a.cnt[C_IF0 + p]), nng = clamp(a.cnt[C_NEWG]),
-                  nfl = clamp(a.cnt[C_FROML]);
-    const long long total = (long long)nold + nng + nfl;
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    // every lane of a wave runs the same number of iterations so the
-    // wave-level appends stay convergent
-    const long long first = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long iters = (total + stride - 1) / stride;
-    for (long long it = 0; it < iters; ++it) {
-        long long k = first + it * stride;
-        bool in = k < total;
+    const long long N = a.g.N;
+    const long long nng = clamp_cap(a, a.cnt[C_NEWG]), nold = clamp_cap(a, a.cnt[C_IF0 + p]),
+                    nfl = clamp_cap(a, a.cnt[C_FROML]);
+    const long long R = (nng * 32 + 63) / 64 * 64;   // refill lanes, whole wavefronts
+    FOR_UNIFORM(t, in, R + nold + nfl) {
         bool is_if = false, conv = false;
         long long gid = 0;
-        if (in) {
+        if (t < R) {
+            // refill: a wavefront never mixes with the items below
+            const long long cell = t >> 5;
+            const bool active = in && cell < nng;
+            const long long g0 = active ? a.list_newg[cell] : 0;
+            refill_group<ST, SCHEME>(a, g0, int(t & 31), active);
+            gid = g0;
+            is_if = active && (t & 31) == 0;
+        } else if (in) {
+            const long long k = t - R;
+            gid = k < nold ? a.list_old[k] : a.list_froml[k - nold];
+            const Cell c = decode(a.g, gid);
+            const long long cbase = (long long)c.b * N;
             if (k < nold) {
-                gid = a.list_old[k];
-                uint8_t fl = a.flags[gid];
-                if (fl & F_MARK_A) {
-                    a.mex[gid] = a.m[gid] - rho_after<ST>(a, gid);
-                    a.flags[gid] = uint8_t(F_LIQ | F_CONV);
-                    a.phi[gid] = 1.0;
-                    a.m[gid] = 0.0;
-                    conv = true;
-                } else if (fl & F_MARK_B) {
-                    a.mex[gid] = a.m[gid];
-                    a.flags[gid] = uint8_t(F_GAS | F_CONV);
-                    a.phi[gid] = 0.0;
+                const uint8_t fl = a.flags[gid];
+                if (fl & (F_MARK_A | F_MARK_B)) {
+                    const bool fill = (fl & F_MARK_A) != 0;
+                    int nb[Q];
+                    neighbours(a.g, c, nb);
+                    uint8_t fq[Q];
+#pragma unroll
+                    for (int i = 1; i < Q; ++i) fq[i] = a.flags[cbase + (nb[i] >= 0 ? nb[i] : c.n)];
+                    double d[Q];
+                    const double mx = fill ? a.m[gid] - rho_after<ST>(a, c, d) : a.m[gid];
+                    int nr = 0;
+#pragma unroll
+                    for (int i = 1; i < Q; ++i) nr += (nb[i] >= 0 && type_after(fq[i]) == F_IF) ? 1 : 0;
+                    if (nr == 0) {
+                        atomicAdd(a.res + p * a.B + c.b, mx);
+                        a.mex[gid] = 0.0;
+                    } else {
+                        a.mex[gid] = mx / nr;
+                    }
+                    a.flags[gid] = uint8_t((fill ? F_LIQ : F_GAS) | F_CONV);
                     a.m[gid] = 0.0;
                     conv = true;
                 } else {
                     is_if = true;
                 }
-            } else if (k < (long long)nold + nng) {
-                gid = a.list_newg[k - nold];
-                a.flags[gid] = F_IF;
-                is_if = true;
             } else {
-                gid = a.list_froml[k - nold - nng];
-                a.m[gid] = rho_after<ST>(a, gid);
-                a.phi[gid] = 1.0;
+                // from liquid: mass = density; keep a copy of its populations
+                double d[Q];
+                a.m[gid] = rho_after<ST>(a, c, d);
+#pragma unroll
+                for (int i = 1; i < Q; ++i) store_fo<ST>(a, i, gid, d[i]);
                 a.flags[gid] = F_IF;
                 is_if = true;
             }
@@ -560,12 +687,12 @@ __global__ void k_apply(StepArgs a) {
         wave_append(conv, int32_t(gid), a.list_conv, a.cnt + C_CONV0 + p, a.cap, a.cnt + C_ERR);
         wave_append(is_if, int32_t(gid), a.list_new, a.cnt + C_IF0 + (1 - p), a.cap, a.cnt + C_ERR);
         // interface cells per domain (one atomic per wave when it is one domain)
-        int b = is_if ? int(gid / a.g.N) : -1;
-        unsigned long long mask = __ballot(is_if);
+        const int b = is_if ? int(a.g.dN.div(uint32_t(gid))) : -1;
+        const unsigned long long mask = __ballot(is_if);
         if (mask) {
-            int lead = __ffsll((long long)mask) - 1;
-            int b0 = __shfl(b, lead);
-            bool same = __ballot(is_if && b != b0) == 0;
+            const int lead = __ffsll((long long)mask) - 1;
+            const int b0 = __shfl(b, lead);
+            const bool same = __ballot(is_if && b != b0) == 0;
             if (same) {
                 if (__lane_id() == lead) atomicAdd(a.nif_dom + p * a.B + b0, __popcll(mask));
             } else if (is_if) {
@@ -575,57 +702,58 @@ __global__ void k_apply(StepArgs a) {
     }
 }
 
-// Receivers of each converted cell's excess mass: its D3Q19 neighbours that are
-// interface after the conversion.  No receiver: the mass goes to the reservoir.
-__global__ void k_excess_gather(StepArgs a) {
+// Every interface cell of the next list gathers the shares of its converted
+// neighbours and the reservoir share, refreshes phi = m/rho if its mass
+// changed, and gets its type and forced filling/emptying class for the next
+// step.  Converted cells get phi in {0, 1} in both fill-level buffers.  Block 0
+// resets the list counters the next step appends to first and carries the
+// reservoir over.
+template <int ST>
+__global__ __launch_bounds__(256) void k_excess(StepArgs a) {
     const int p = a.parity;
-    const int32_t nc = a.cnt[C_CONV0 + p];
-    FOR_LIST(k, nc) {
-        long long gid = a.list_conv[k];
-        Cell c = decode(a.g, gid);
-        int nr = 0;
-#pragma unroll
-        for (int i = 1; i < Q; ++i) {
-            long long q = nb_dir(a.g, c, i);
-            if (q >= 0 && (a.flags[q] & F_IF)) ++nr;
+    const long long N = a.g.N;
+    if (blockIdx.x == 0) {
+        for (int b = threadIdx.x; b < a.B; b += blockDim.x) {
+            // mass that found no receiver is kept while the domain has no interface
+            a.res[(1 - p) * a.B + b] = a.nif_dom[p * a.B + b] > 0 ? 0.0 : a.res[p * a.B + b];
+            a.nif_dom[(1 - p) * a.B + b] = 0;
         }
-        if (nr == 0) {
-            atomicAdd(a.res + p * a.B + c.b, a.mex[gid]);
-            a.mex[gid] = 0.0;
-        } else {
-            a.mex[gid] = a.mex[gid] / nr;
+        if (threadIdx.x == 0) {
+            a.cnt[C_IF0 + p] = 0;   // this step's list is dead; the next step appends to it
+            a.cnt[C_BAND] = 0;
         }
     }
-}
-
-// Every interface cell gathers the shares of its converted neighbours and the
-// reservoir share, refreshes phi = m/rho if its mass changed, and gets its
-// forced filling/emptying class for the next step.
-template <int ST>
-__global__ void k_excess_scatter(StepArgs a) {
-    const int p = a.parity;
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.cnt[C_BAND] = 0;
-    const int32_t nn = a.cnt[C_IF0 + (1 - p)];
-    FOR_LIST(k, nn) {
-        long long gid = a.list_new[k];
-        Cell c = decode(a.g, gid);
+    const double *res = a.res + p * a.B;
+    const int32_t *nif = a.nif_dom + p * a.B;
+    FOR_LIST(k, a.cnt[C_IF0 + (1 - p)]) {
+        const long long gid = a.list_new[k];
+        const Cell c = decode(a.g, gid);
+        const long long cbase = (long long)c.b * N;
+        int nb[Q];
+        neighbours(a.g, c, nb);
+        uint8_t fq[Q];
+        double mx[Q];
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const long long q = cbase + (nb[i] >= 0 ? nb[i] : c.n);
+            fq[i] = nb[i] >= 0 ? a.flags[q] : uint8_t(0);
+            mx[i] = a.mex[q];
+        }
         double add = 0.0;
         bool touched = false, has_liq = false, has_gas = false;
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
-            long long q = nb_dir(a.g, c, i);
-            if (q < 0) continue;
-            uint8_t fq = a.flags[q];
-            if (fq & F_CONV) {
+            if (fq[i] & F_CONV) {
                 // a converted neighbour that had receivers (it has at least this one)
-                add += a.mex[q];
+                add += mx[i];
                 touched = true;
             }
-            has_liq |= (fq & F_LIQ) != 0;
-            has_gas |= (fq & F_GAS) != 0;
+            const uint8_t ty = type_after(fq[i]);
+            has_liq |= ty == F_LIQ;
+            has_gas |= ty == F_GAS;
         }
-        double r = a.res[p * a.B + c.b];
-        int nd = a.nif_dom[p * a.B + c.b];
+        const double r = res[c.b];
+        const int nd = nif[c.b];
         double m = a.m[gid];
         if (touched) m = m + add;
         if (r != 0.0 && nd > 0) {
@@ -633,51 +761,78 @@ __global__ void k_excess_scatter(StepArgs a) {
             touched = true;
         }
         if (touched) {
+            double d[Q];
             a.m[gid] = m;
-            a.phi[gid] = m / rho_after<ST>(a, gid);
+            a.phi_next[gid] = m / rho_after<ST>(a, c, d);
         }
         a.flags[gid] = uint8_t(F_IF | (!has_liq ? F_NOFLUID : (!has_gas ? F_NOEMPTY : 0)));
+    }
+    FOR_LIST(k, a.cnt[C_CONV0 + p]) {
+        const long long gid = a.list_conv[k];
+        const double v = (a.flags[gid] & F_LIQ) ? 1.0 : 0.0;
+        a.phi_cur[gid] = v;
+        a.phi_next[gid] = v;
     }
 }
 
 // ------------------------------------------------------------------ launchers
 
+// List kernels get a fixed grid (the list lengths are only known on the
+// device); 2048 workgroups cover 512k items per pass.
 static int list_blocks(long long cap) {
     long long b = (cap + 255) / 256;
-    return int(b < 1024 ? (b < 1 ? 1 : b) : 1024);
+    return int(b < 2048 ? (b < 1 ? 1 : b) : 2048);
+}
+
+template <typename K>
+static void launch_bulk(K kernel, const StepArgs &a, hipStream_t s) {
+    const unsigned blocks = unsigned((a.g.BN + 255) / 256);
+    hipLaunchKernelGGL(kernel, dim3(blocks), dim3(256), 0, s, a);
 }
 
 template <int ST>
 static void launch_step_t(const StepArgs &a, int collision, int scheme, hipStream_t s,
-                          const BulkEvents *ev) {
+                          const BulkEvents *ev, const SideStream &side) {
     const int lb = list_blocks(a.cap);
     if (a.rhoG) {
         hipLaunchKernelGGL(k_band, dim3(lb), dim3(256), 0, s, a);
         hipLaunchKernelGGL(k_normals, dim3(lb), dim3(256), 0, s, a);
         hipLaunchKernelGGL(k_curvature, dim3(lb), dim3(256), 0, s, a);
     }
-    hipLaunchKernelGGL(k_mass_exchange<ST>, dim3(lb), dim3(256), 0, s, a);
-    const unsigned nblk = unsigned((a.g.BN + 255) / 256);
+    // fork: interface cells on the side stream, liquid cells on the main one.
+    // The interface kernel gets a small grid: it only has to finish within the
+    // bulk kernel's time, and every resident interface wavefront holds half a
+    // SIMD's registers that the bulk kernel would otherwise use.
+    const int ib = lb < 256 ? lb : 256;
+    (void)hipEventRecord(side.fork, s);
+    (void)hipStreamWaitEvent(side.stream, side.fork, 0);
+    if (collision == 0) {
+        if (a.parity == 0) hipLaunchKernelGGL((k_interface<ST, 0, 0>), dim3(ib), dim3(256), 0, side.stream, a);
+        else hipLaunchKernelGGL((k_interface<ST, 0, 1>), dim3(ib), dim3(256), 0, side.stream, a);
+    } else {
+        if (a.parity == 0) hipLaunchKernelGGL((k_interface<ST, 1, 0>), dim3(ib), dim3(256), 0, side.stream, a);
+        else hipLaunchKernelGGL((k_interface<ST, 1, 1>), dim3(ib), dim3(256), 0, side.stream, a);
+    }
+    (void)hipEventRecord(side.join, side.stream);
     if (ev) (void)hipEventRecord(ev->before, s);
     if (collision == 0) {
-        if (a.parity == 0) hipLaunchKernelGGL((k_stream_collide<ST, 0, 0>), dim3(nblk), dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((k_stream_collide<ST, 0, 1>), dim3(nblk), dim3(256), 0, s, a);
+        if (a.parity == 0) launch_bulk(k_stream_collide<ST, 0, 0>, a, s);
+        else launch_bulk(k_stream_collide<ST, 0, 1>, a, s);
     } else {
-        if (a.parity == 0) hipLaunchKernelGGL((k_stream_collide<ST, 1, 0>), dim3(nblk), dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((k_stream_collide<ST, 1, 1>), dim3(nblk), dim3(256), 0, s, a);
+        if (a.parity == 0) launch_bulk(k_stream_collide<ST, 1, 0>, a, s);
+        else launch_bulk(k_stream_collide<ST, 1, 1>, a, s);
     }
     if (ev) (void)hipEventRecord(ev->after, s);
+    (void)hipStreamWaitEvent(s, side.join, 0);   // join
     hipLaunchKernelGGL(k_resolve, dim3(lb), dim3(256), 0, s, a);
     switch (scheme) {
-        case 0: hipLaunchKernelGGL((k_refill<ST, 0>), dim3(lb), dim3(256), 0, s, a); break;
-        case 1: hipLaunchKernelGGL((k_refill<ST, 1>), dim3(lb), dim3(256), 0, s, a); break;
-        case 2: hipLaunchKernelGGL((k_refill<ST, 2>), dim3(lb), dim3(256), 0, s, a); break;
-        case 3: hipLaunchKernelGGL((k_refill<ST, 3>), dim3(lb), dim3(256), 0, s, a); break;
-        default: hipLaunchKernelGGL((k_refill<ST, 4>), dim3(lb), dim3(256), 0, s, a); break;
+        case 0: hipLaunchKernelGGL((k_convert<ST, 0>), dim3(lb), dim3(256), 0, s, a); break;
+        case 1: hipLaunchKernelGGL((k_convert<ST, 1>), dim3(lb), dim3(256), 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_convert<ST, 2>), dim3(lb), dim3(256), 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_convert<ST, 3>), dim3(lb), dim3(256), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_convert<ST, 4>), dim3(lb), dim3(256), 0, s, a); break;
     }
-    hipLaunchKernelGGL(k_apply<ST>, dim3(lb), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_excess_gather, dim3(lb), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_excess_scatter<ST>, dim3(lb), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_excess<ST>, dim3(lb), dim3(256), 0, s, a);
 }
 
 }  // namespace
@@ -685,19 +840,20 @@ static void launch_step_t(const StepArgs &a, int collision, int scheme, hipStrea
 #if defined(FSLBM_UNIT_STORAGE)
 template <>
 void launch_step_storage<FSLBM_UNIT_STORAGE>(const StepArgs &a, int collision, int scheme,
-                                             hipStream_t s, const BulkEvents *ev) {
-    launch_step_t<FSLBM_UNIT_STORAGE>(a, collision, scheme, s, ev);
+                                             hipStream_t s, const BulkEvents *ev,
+                                             const SideStream &side) {
+    launch_step_t<FSLBM_UNIT_STORAGE>(a, collision, scheme, s, ev, side);
 }
 #endif
 
 #if defined(FSLBM_UNIT_DISPATCH)
 void launch_step(const StepArgs &a, int storage, int collision, int scheme, hipStream_t s,
-                 const BulkEvents *ev) {
+                 const SideStream &side, const BulkEvents *ev) {
     switch (storage) {
-        case ST_F64: launch_step_storage<ST_F64>(a, collision, scheme, s, ev); break;
-        case ST_F32: launch_step_storage<ST_F32>(a, collision, scheme, s, ev); break;
-        case ST_F16: launch_step_storage<ST_F16>(a, collision, scheme, s, ev); break;
-        default: launch_step_storage<ST_BF16>(a, collision, scheme, s, ev); break;
+        case ST_F64: launch_step_storage<ST_F64>(a, collision, scheme, s, ev, side); break;
+        case ST_F32: launch_step_storage<ST_F32>(a, collision, scheme, s, ev, side); break;
+        case ST_F16: launch_step_storage<ST_F16>(a, collision, scheme, s, ev, side); break;
+        default: launch_step_storage<ST_BF16>(a, collision, scheme, s, ev, side); break;
     }
 }
 #endif

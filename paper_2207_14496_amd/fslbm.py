@@ -30,7 +30,7 @@ STORAGE_BYTES = {F64: 8, F32: 4, F16: 2, BF16: 2}
 SYMBOLS = ["fslbm_workspace_bytes", "fslbm_init", "fslbm_step", "fslbm_step_timed",
            "fslbm_refill_scheme",
            "fslbm_use_graphs", "fslbm_set_stream", "fslbm_read_fields", "fslbm_diagnostics",
-           "fslbm_last_error", "fslbm_destroy"]
+           "fslbm_last_step_stats", "fslbm_last_error", "fslbm_destroy"]
 
 
 class FslbmError(RuntimeError):
@@ -57,6 +57,11 @@ class CDiag(ctypes.Structure):
                 ("finite", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
+class CStepStats(ctypes.Structure):
+    _fields_ = [("interface_cells", ctypes.c_int64), ("new_from_gas", ctypes.c_int64),
+                ("from_liquid", ctypes.c_int64), ("converted", ctypes.c_int64)]
+
+
 _lib = None
 
 
@@ -78,6 +83,8 @@ def lib() -> ctypes.CDLL:
         L.fslbm_set_stream.argtypes = [vp, vp]
         L.fslbm_read_fields.argtypes = [vp, ctypes.c_uint32, P(vp)]
         L.fslbm_diagnostics.argtypes = [vp, P(CDiag)]
+        L.fslbm_last_step_stats.argtypes = [vp, P(CStepStats)]
+        L.fslbm_last_step_stats.restype = ctypes.c_int
         L.fslbm_last_error.argtypes = [vp]
         L.fslbm_last_error.restype = ctypes.c_char_p
         L.fslbm_destroy.argtypes = [vp]
@@ -250,6 +257,12 @@ class Simulation:
                         "n_interface": d.n_interface, "n_gas": d.n_gas,
                         "finite": bool(d.finite), "stable": st != EUNSTABLE})
         return out
+
+    def last_step_stats(self) -> dict:
+        """List sizes of the most recent step (all domains)."""
+        st = CStepStats()
+        _check(lib().fslbm_last_step_stats(self._ctx, ctypes.byref(st)), self._ctx)
+        return {k: getattr(st, k) for k, _ in CStepStats._fields_}
 
     def close(self):
         if getattr(self, "_ctx", None):
