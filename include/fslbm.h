@@ -35,7 +35,8 @@
  *   (0,1,-1) (0,-1,1); the opposite of i >= 1 is i+1 (odd i) or i-1 (even i).
  * - Memory: the caller owns every byte.  The library never allocates device
  *   memory; it carves the caller's workspace (fslbm_workspace_bytes) and keeps
- *   only a small host-side context.  Inputs are read, never retained.
+ *   only a small host-side context.  Inputs are read, never retained (the
+ *   adjoint target pointer is the one exception, see fslbm_adjoint_spec).
  * - Streams: all device work is enqueued on params.stream (a hipStream_t;
  *   NULL = the null stream).  fslbm_init, fslbm_read_fields and
  *   fslbm_diagnostics synchronise that stream before returning; fslbm_step
@@ -199,6 +200,65 @@ typedef struct fslbm_step_stats {
 /* Fill *out with the conversion activity of the last step (zeros before the
  * first step).  Synchronises. */
 fslbm_status fslbm_last_step_stats(fslbm_ctx *ctx, fslbm_step_stats *out);
+
+/*
+ * Reverse mode: an interface-height loss over a window of T steps and its
+ * gradient.  The paper does not differentiate the method; this is the adjoint
+ * of the step (a), (b), (d) and (e) above, taken with the sequence of cell
+ * types (and so every conversion decision) held fixed at what the forward run
+ * produced.  Per domain b,
+ *     L_b = (1/T) sum_{t=1..T} (h_b(t) - h*_b(t))^2,
+ *     h_b(t) = sum of the fill level phi(t) over the cells with x = x_probe.
+ * Differentiated quantities: omega_b, g_b, and the canonical state the window
+ * starts from (f*, m, phi).  The reservoir of excess mass is part of the state
+ * and is differentiated through.
+ * Supported configuration: FSLBM_F64 storage, FSLBM_SRT, sigma = 0 and
+ * FSLBM_REFILL_EQ (each call returns FSLBM_EINVAL otherwise); batch <= 65535.
+ * Memory: sqrt(T)-style checkpointing.  The forward keeps K states; the
+ * backward recomputes one segment of ceil(T/K) steps at a time from its
+ * checkpoint and runs the reverse steps over it.
+ */
+typedef struct fslbm_adjoint_spec {
+    int32_t nsteps;          /* T >= 1 steps in the window                          */
+    int32_t n_checkpoints;   /* K in [1, T] stored states; 0 selects ceil(sqrt(T))  */
+    int32_t x_probe;         /* probe plane, 0 <= x_probe < nx                      */
+    int32_t pad;
+    const double *target;    /* DEVICE [B][T]: h*_b(t) for t = 1..T; read by both   */
+                             /* calls, so it must stay valid until the backward     */
+} fslbm_adjoint_spec;
+
+/* Bytes of the separate device workspace (256-byte aligned, owned by the
+ * caller) that fslbm_adjoint_forward / _backward need for this spec. */
+fslbm_status fslbm_adjoint_workspace_bytes(fslbm_ctx *ctx, const fslbm_adjoint_spec *spec,
+                                           size_t *bytes);
+
+/*
+ * Run the T steps of the window from the context's current state, storing the
+ * checkpoints in `workspace`.  loss: HOST [B] receives L_b.  height: HOST
+ * [B][T+1] receives h_b(0..T), or NULL.  Synchronises.  Afterwards the context
+ * holds the state at the end of the window.  Every checkpoint is written out
+ * and read back, and the run continues from what was read, so the forward run
+ * and the backward's recomputation produce bit-identical states.
+ */
+fslbm_status fslbm_adjoint_forward(fslbm_ctx *ctx, const fslbm_adjoint_spec *spec, void *workspace,
+                                   size_t bytes, double *loss, double *height);
+
+/*
+ * Gradient of sum_b dloss[b] * L_b for the window of the last
+ * fslbm_adjoint_forward on this context (same spec and workspace).
+ *   dloss         HOST [B], or NULL for all ones.
+ *   grad_omega    HOST [B]      dL/d omega_b.
+ *   grad_gravity  HOST [B][3]   dL/d g_b.
+ *   grad_pdf0     DEVICE [B][19][N] dL/d f*(x, start) (0 in gas), or NULL.
+ *   grad_mass0    DEVICE [B][N]  dL/d m(x, start) (0 off the interface), or NULL.
+ *   grad_phi0     DEVICE [B][N]  dL/d phi(x, start) (0 off the interface), or NULL.
+ * May be called again with another dloss.  Synchronises.  Afterwards the
+ * context holds the state at the end of the window again.
+ */
+fslbm_status fslbm_adjoint_backward(fslbm_ctx *ctx, const fslbm_adjoint_spec *spec, void *workspace,
+                                    size_t bytes, const double *dloss, double *grad_omega,
+                                    double *grad_gravity, double *grad_pdf0, double *grad_mass0,
+                                    double *grad_phi0);
 
 /* Text of the first error seen by this context (or by the last failed init
  * when ctx is NULL).  Never NULL. */

@@ -24,6 +24,8 @@ UNITS = [
     ("step_kernels.hip", ["-DFSLBM_UNIT_STORAGE=2"]),
     ("step_kernels.hip", ["-DFSLBM_UNIT_STORAGE=3"]),
     ("step_kernels.hip", ["-DFSLBM_UNIT_DISPATCH=1"]),
+    ("adjoint_kernels.hip", []),
+    ("adjoint_api.hip", []),
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

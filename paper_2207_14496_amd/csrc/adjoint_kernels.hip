@@ -1,0 +1,553 @@
+// adjoint_kernels.hip -- reverse mode of one FSLBM step (FP64, SRT collision,
+// EQ refilling, no surface tension) with the cell-type sequence frozen from the
+// forward run.
+//
+// The forward step t -> t+1 on the canonical state (post-collision PDFs f*,
+// interface mass m, fill level phi, cell types, reservoir) is
+//   S1  streaming with bounce-back at walls (Sec. 2.1) and anti-bounce-back
+//       from gas cells (Sec. 2.2, with the cell's velocity from f*(t) and the
+//       gas density rho_G = 3 p_V); interface mass exchange
+//       m' = m + sum_i dm_i(f*(t), phi(t), forced classes) (Sec. 2.2, mass
+//       flux equation); phi' = m' / rho with rho the streamed density
+//   S2  SRT collision with Guo forcing, F = rho g (Sec. 2.1)
+//   S5  EQ refilling of new interface cells from the mean density and velocity
+//       of their valid neighbours (Sec. 3.1)
+//   S6  conversions: a filled cell's excess is m' - rho*, an emptied cell's is
+//       m'; a cell that leaves the liquid gets m = rho* (Sec. 2.2)
+//   S7  excess shares to the interface neighbours after S6, or to the
+//       domain's reservoir, which is spread over all interface cells;
+//       phi = m / rho* on every cell whose mass changed (Sec. 2.2, excess-mass
+//       equation).
+// Its reverse runs S7/S6 (k_adj_receivers, k_adj_converted), S5
+// (k_adj_refill), S2 with phi' (k_adj_collide) and S1 as a gather over the
+// source cell (k_adj_stream).  Which cells converted, and which interface cells
+// received excess mass, is read off the two canonical type fields; the
+// conversion decisions themselves are held fixed.
+#include "adjoint.hpp"
+
+namespace fslbm {
+namespace {
+
+constexpr int BS = 256;
+
+__device__ __forceinline__ Cell cell_of(const Geom &g, int b, int n) {
+    Cell c;
+    c.b = b;
+    c.n = n;
+    const uint32_t r = g.dx.div(uint32_t(n));
+    const uint32_t z = g.dy.div(r);
+    c.x = n - int(r) * g.nx;
+    c.y = int(r) - int(z) * g.ny;
+    c.z = int(z);
+    return c;
+}
+
+// Flat index of PDF i of cell n in domain b ([B][19][N]).
+__device__ __forceinline__ long long pidx(const Geom &g, int b, int i, int n) {
+    return ((long long)b * Q + i) * g.N + n;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// dst[k] += sum over the workgroup of v[k] (fixed order; every thread calls).
+__device__ __forceinline__ void block_add4(double (&v)[4], double *dst) {
+    __shared__ double sh[BS / 64][4];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double s = wave_sum(v[k]);
+        if (lane == 0) sh[w][k] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) dst[k] += (sh[0][k] + sh[1][k]) + (sh[2][k] + sh[3][k]);
+    }
+}
+
+enum { STD = 0, NOFLUID = 1, NOEMPTY = 2 };
+
+// Forced filling/emptying class of an interface cell from the types around it.
+__device__ __forceinline__ int type_class(const Geom &g, const uint8_t *fl, const Cell &c) {
+    bool liq = false, gas = false;
+    const long long cb = (long long)c.b * g.N;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const int q = nb_local(g, c.x, c.y, c.z, cx(i), cy(i), cz(i));
+        if (q < 0) continue;
+        liq |= fl[cb + q] == F_LIQ;
+        gas |= fl[cb + q] == F_GAS;
+    }
+    return !liq ? NOFLUID : (!gas ? NOEMPTY : STD);
+}
+
+// The interface-interface link flux under the forced classes is
+// ca * fin + cb * fout (cc: the cell's class, cn: the neighbour's).
+__device__ __forceinline__ void flux_coef(int cc, int cn, double &ca, double &cb) {
+    if (cc == cn) { ca = 1.0; cb = -1.0; }
+    else if (cc == STD) { if (cn == NOFLUID) { ca = 1.0; cb = 0.0; } else { ca = 0.0; cb = -1.0; } }
+    else if (cc == NOFLUID) { ca = 0.0; cb = -1.0; }
+    else { ca = 1.0; cb = 0.0; }
+}
+
+// Streamed (pre-collision) populations of fluid cell c at t+1 from f*(t).
+__device__ __forceinline__ void stream_in(const AdjArgs &a, const Cell &c, double (&fin)[Q]) {
+    const double *f0 = a.s0.f;
+    const uint8_t *fl = a.s0.fl;
+    const long long cb = (long long)c.b * a.g.N;
+    double fs[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) fs[i] = f0[pidx(a.g, c.b, i, c.n)];
+    double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        r += fs[i];
+        jx += cx(i) * fs[i]; jy += cy(i) * fs[i]; jz += cz(i) * fs[i];
+    }
+    const double *gr = a.grav + 3 * c.b;
+    const double ux = jx / r - 0.5 * gr[0], uy = jy / r - 0.5 * gr[1], uz = jz / r - 0.5 * gr[2];
+    const double uu = ux * ux + uy * uy + uz * uz;
+    fin[0] = fs[0];
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const int s = nb_local(a.g, c.x, c.y, c.z, -cx(i), -cy(i), -cz(i));
+        if (s < 0) {
+            fin[i] = fs[opp(i)];
+        } else if (fl[cb + s] == F_GAS) {
+            const double uc = cx(i) * ux + cy(i) * uy + cz(i) * uz;
+            fin[i] = 2.0 * wgt<double>(i) * a.rhoG * (1.0 + 4.5 * uc * uc - 1.5 * uu) - fs[opp(i)];
+        } else {
+            fin[i] = f0[pidx(a.g, c.b, i, s)];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ kernels
+
+// Forced classes of the interface cells at t.
+__global__ __launch_bounds__(BS) void k_adj_classes(AdjArgs a) {
+    const int b = blockIdx.y, n = blockIdx.x * BS + threadIdx.x;
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.sum_lm[b] = 0.0;
+    if (n >= a.g.N) return;
+    const long long gid = (long long)b * a.g.N + n;
+    a.cls[gid] = a.s0.fl[gid] == F_IF ? uint8_t(type_class(a.g, a.s0.fl, cell_of(a.g, b, n))) : 0;
+}
+
+// S7 reverse on the cells that are interface at t+1.  The loss adds its
+// fill-level adjoint on the probe plane.  A cell whose mass changed (a
+// converted neighbour, or the domain's reservoir spread) had phi = m / rho*:
+// that adjoint moves to m and f*.  An unchanged cell that was already
+// interface keeps phi = phi'.
+__global__ __launch_bounds__(BS) void k_adj_receivers(AdjArgs a) {
+    const int b = blockIdx.y, n = blockIdx.x * BS + threadIdx.x;
+    if (n >= a.g.N) return;
+    const long long gid = (long long)b * a.g.N + n;
+    const uint8_t ty0 = a.s0.fl[gid], ty1 = a.s1.fl[gid];
+    double lphis = 0.0;
+    if (ty1 == F_IF) {
+        const Cell c = cell_of(a.g, b, n);
+        const long long cb = (long long)b * a.g.N;
+        const bool spread = a.s1.R[b] != 0.0 && a.s1.nif[b] > 0;
+        double lp = a.lphi1[gid];
+        if (c.x == a.x_probe)
+            lp += 2.0 * (a.h[(long long)b * (a.T + 1) + a.t1] - a.target[(long long)b * a.T + (a.t1 - 1)]) /
+                  a.T * a.dloss[b];
+        bool touched = spread;
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const int q = nb_local(a.g, c.x, c.y, c.z, cx(i), cy(i), cz(i));
+            if (q < 0) continue;
+            touched |= a.s0.fl[cb + q] == F_IF && a.s1.fl[cb + q] != F_IF;
+        }
+        if (touched) {
+            double rs = 0.0;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) rs += a.s1.f[pidx(a.g, b, i, n)];
+            const double lm = a.lm1[gid] + lp / rs;
+            a.lm1[gid] = lm;
+            const double dr = -lp * a.s1.m[gid] / (rs * rs);
+#pragma unroll
+            for (int i = 0; i < Q; ++i) a.lf1[pidx(a.g, b, i, n)] += dr;
+            if (spread) atomicAdd(a.sum_lm + b, lm);
+        } else if (ty0 == F_IF) {
+            lphis = lp;
+        }
+    }
+    a.lphis[gid] = lphis;
+}
+
+// S6/S7 reverse on converted cells and on cells that left the liquid; sets the
+// adjoint of m' of every cell that was interface at t, and of the reservoir.
+__global__ __launch_bounds__(BS) void k_adj_converted(AdjArgs a) {
+    const int b = blockIdx.y, n = blockIdx.x * BS + threadIdx.x;
+    if (n >= a.g.N) return;
+    const long long gid = (long long)b * a.g.N + n;
+    const bool spread = a.s1.R[b] != 0.0 && a.s1.nif[b] > 0;
+    // the reservoir after S7 is 0 when spread, else reservoir + unreceived excess
+    const double lR = spread ? a.sum_lm[b] / a.s1.nif[b] : a.lres1[b];
+    if (n == 0) a.lres0[b] = lR;
+    const uint8_t ty0 = a.s0.fl[gid], ty1 = a.s1.fl[gid];
+    double lmt = 0.0;
+    if (ty0 == F_LIQ && ty1 == F_IF) {
+        const double l = a.lm1[gid];   // m = rho* (+ shares)
+#pragma unroll
+        for (int i = 0; i < Q; ++i) a.lf1[pidx(a.g, b, i, n)] += l;
+    } else if (ty0 == F_IF && ty1 != F_IF) {
+        const Cell c = cell_of(a.g, b, n);
+        const long long cb = (long long)b * a.g.N;
+        int nr = 0;
+        double s = 0.0;
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const int q = nb_local(a.g, c.x, c.y, c.z, cx(i), cy(i), cz(i));
+            if (q < 0 || a.s1.fl[cb + q] != F_IF) continue;
+            ++nr;
+            s += a.lm1[cb + q];
+        }
+        const double lmex = nr > 0 ? s / nr : lR;
+        lmt = lmex;   // the excess is m' - rho* (filled) or m' (emptied)
+        if (ty1 == F_LIQ) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) a.lf1[pidx(a.g, b, i, n)] -= lmex;
+        }
+    } else if (ty0 == F_IF && ty1 == F_IF) {
+        lmt = a.lm1[gid];
+    }
+    a.lmt[gid] = lmt;
+}
+
+// S5 reverse (EQ refilling): the new cell's PDFs are f_eq(rho_bar, u_bar) over
+// its valid neighbours v (liquid, or interface and not emptied, at t), with
+// rho(v) = sum f*(v) and u(v) = sum c f*(v) / rho(v) - g/2 at t+1.  A source
+// can feed several new cells, so its adjoint is accumulated atomically.
+__device__ __forceinline__ bool refill_source(const AdjArgs &a, long long cb, int q) {
+    if (q < 0) return false;
+    const uint8_t t0 = a.s0.fl[cb + q], t1 = a.s1.fl[cb + q];
+    return t0 == F_LIQ || (t0 == F_IF && t1 != F_GAS);
+}
+
+// Density and velocity sum c f* / rho - g/2 of cell q at t+1.
+__device__ __forceinline__ void moments1(const AdjArgs &a, int b, int q, const double *gr, double &r,
+                                         double (&u)[3]) {
+    double j[3] = {0.0, 0.0, 0.0};
+    r = 0.0;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        const double v = a.s1.f[pidx(a.g, b, k, q)];
+        r += v;
+        j[0] += cx(k) * v; j[1] += cy(k) * v; j[2] += cz(k) * v;
+    }
+    for (int d = 0; d < 3; ++d) u[d] = j[d] / r - 0.5 * gr[d];
+}
+
+__global__ __launch_bounds__(BS) void k_adj_refill(AdjArgs a) {
+    const int b = blockIdx.y, n = blockIdx.x * BS + threadIdx.x;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const long long gid = (long long)b * a.g.N + n;
+    if (n < a.g.N && a.s0.fl[gid] == F_GAS && a.s1.fl[gid] == F_IF) {
+        const Cell c = cell_of(a.g, b, n);
+        const long long cb = (long long)b * a.g.N;
+        const double *gr = a.grav + 3 * b;
+        int nv = 0;
+        double rs = 0.0, us[3] = {0.0, 0.0, 0.0};
+#pragma unroll 1
+        for (int i = 1; i < Q; ++i) {
+            const int q = nb_local(a.g, c.x, c.y, c.z, k_cx[i], k_cy[i], k_cz[i]);
+            if (!refill_source(a, cb, q)) continue;
+            double r, u[3];
+            moments1(a, b, q, gr, r, u);
+            ++nv;
+            rs += r;
+            for (int d = 0; d < 3; ++d) us[d] += u[d];
+        }
+        if (nv > 0) {
+            const double rb = rs / nv;
+            const double ub[3] = {us[0] / nv, us[1] / nv, us[2] / nv};
+            const double uu = ub[0] * ub[0] + ub[1] * ub[1] + ub[2] * ub[2];
+            double lrb = 0.0, lub[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const double l = a.lf1[pidx(a.g, b, i, n)];
+                const double uc = cx(i) * ub[0] + cy(i) * ub[1] + cz(i) * ub[2];
+                const double w = wgt<double>(i);
+                lrb += l * w * (1.0 + 3.0 * uc + 4.5 * uc * uc - 1.5 * uu);
+                const int ci[3] = {cx(i), cy(i), cz(i)};
+                for (int d = 0; d < 3; ++d) lub[d] += l * w * rb * (3.0 * ci[d] + 9.0 * uc * ci[d] - 3.0 * ub[d]);
+            }
+            const double lr = lrb / nv;
+            const double lu[3] = {lub[0] / nv, lub[1] / nv, lub[2] / nv};
+            // rho(v) and u(v) = sum c f*(v) / rho(v) - g/2 of every source v
+#pragma unroll 1
+            for (int i = 1; i < Q; ++i) {
+                const int q = nb_local(a.g, c.x, c.y, c.z, k_cx[i], k_cy[i], k_cz[i]);
+                if (!refill_source(a, cb, q)) continue;
+                double r, u[3];
+                moments1(a, b, q, gr, r, u);
+#pragma unroll
+                for (int k = 0; k < Q; ++k) {
+                    const int ck[3] = {cx(k), cy(k), cz(k)};
+                    double v = lr;
+                    for (int d = 0; d < 3; ++d) v += lu[d] * (ck[d] - (u[d] + 0.5 * gr[d])) / r;
+                    atomicAdd(a.lf1 + pidx(a.g, b, k, q), v);
+                }
+            }
+            for (int d = 0; d < 3; ++d) acc[1 + d] = -0.5 * lub[d];
+        }
+    }
+    block_add4(acc, a.gpart + ((long long)b * a.nblk + blockIdx.x) * 4);
+}
+
+// S2 reverse (SRT collision with Guo forcing) and phi' = m' / rho: adjoint of
+// the streamed populations at t+1 and the phi' part of the adjoint of m'.
+__global__ __launch_bounds__(BS) void k_adj_collide(AdjArgs a) {
+    const int b = blockIdx.y, n = blockIdx.x * BS + threadIdx.x;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const long long gid = (long long)b * a.g.N + n;
+    if (n < a.g.N) {
+        const uint8_t ty0 = a.s0.fl[gid];
+        if (ty0 == F_GAS) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) a.lfin[pidx(a.g, b, i, n)] = 0.0;
+        } else {
+            const Cell c = cell_of(a.g, b, n);
+            double fin[Q];
+            stream_in(a, c, fin);
+            const double *gr = a.grav + 3 * b;
+            const double om = a.omega[b];
+            double rho = 0.0, J[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                rho += fin[i];
+                J[0] += cx(i) * fin[i]; J[1] += cy(i) * fin[i]; J[2] += cz(i) * fin[i];
+            }
+            const double F[3] = {rho * gr[0], rho * gr[1], rho * gr[2]};
+            const double u[3] = {J[0] / rho + 0.5 * gr[0], J[1] / rho + 0.5 * gr[1], J[2] / rho + 0.5 * gr[2]};
+            const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+            const double uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
+            const double pf = 1.0 - 0.5 * om;
+            double lrho = 0.0, lu[3] = {0.0, 0.0, 0.0}, lF[3] = {0.0, 0.0, 0.0}, lom = 0.0;
+            double lam[Q];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const double l = a.lf1[pidx(a.g, b, i, n)];
+                lam[i] = l;
+                const int ci[3] = {cx(i), cy(i), cz(i)};
+                const double w = wgt<double>(i);
+                const double uc = ci[0] * u[0] + ci[1] * u[1] + ci[2] * u[2];
+                const double feq = w * rho * (1.0 + 3.0 * uc + 4.5 * uc * uc - 1.5 * uu);
+                const double cF = ci[0] * F[0] + ci[1] * F[1] + ci[2] * F[2];
+                const double Fh = w * (3.0 * (cF - uF) + 9.0 * uc * cF);
+                lom += l * (-(fin[i] - feq) - 0.5 * Fh);
+                lrho += l * om * feq / rho;
+                for (int d = 0; d < 3; ++d) {
+                    lu[d] += l * (om * w * rho * (3.0 * ci[d] + 9.0 * uc * ci[d] - 3.0 * u[d]) +
+                                  pf * w * (-3.0 * F[d] + 9.0 * ci[d] * cF));
+                    lF[d] += l * pf * w * (3.0 * (ci[d] - u[d]) + 9.0 * uc * ci[d]);
+                }
+            }
+            for (int d = 0; d < 3; ++d) lrho += lF[d] * gr[d];   // F = rho g
+            double lfi[Q];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const int ci[3] = {cx(i), cy(i), cz(i)};
+                double v = (1.0 - om) * lam[i] + lrho;
+                for (int d = 0; d < 3; ++d) v += lu[d] * (ci[d] - (u[d] - 0.5 * gr[d])) / rho;
+                lfi[i] = v;
+            }
+            if (ty0 == F_IF) {
+                const double lp = a.lphis[gid];
+                if (lp != 0.0) {
+                    // phi(t+1) = phi' = m' / rho here
+                    a.lmt[gid] += lp / rho;
+                    const double dr = -lp * a.s1.phi[gid] / rho;
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) lfi[i] += dr;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < Q; ++i) a.lfin[pidx(a.g, b, i, n)] = lfi[i];
+            acc[0] = lom;
+            for (int d = 0; d < 3; ++d) acc[1 + d] = lF[d] * rho + 0.5 * lu[d];
+        }
+    }
+    block_add4(acc, a.gpart + ((long long)b * a.nblk + blockIdx.x) * 4);
+}
+
+// S1 reverse, gathered over the source cell y: every use of f*_i(y) --
+// streamed into y + c_i, bounced back at a wall, inside the anti-bounce-back of
+// y (directly and through u(y)), and in the mass-exchange links of y and of its
+// interface neighbours.  Also the adjoints of m(y, t) and phi(y, t).
+__global__ __launch_bounds__(BS) void k_adj_stream(AdjArgs a) {
+    const int b = blockIdx.y, n = blockIdx.x * BS + threadIdx.x;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const long long gid = (long long)b * a.g.N + n;
+    if (n < a.g.N) {
+        const uint8_t ty0 = a.s0.fl[gid];
+        if (ty0 == F_GAS) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) a.lf0[pidx(a.g, b, i, n)] = 0.0;
+            a.lm0[gid] = 0.0;
+            a.lphi0[gid] = 0.0;
+        } else {
+            const Cell c = cell_of(a.g, b, n);
+            const long long cb = (long long)b * a.g.N;
+            const double *gr = a.grav + 3 * b;
+            double fs[Q];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) fs[i] = a.s0.f[pidx(a.g, b, i, n)];
+            double rs = 0.0, js[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                rs += fs[i];
+                js[0] += cx(i) * fs[i]; js[1] += cy(i) * fs[i]; js[2] += cz(i) * fs[i];
+            }
+            const double ua[3] = {js[0] / rs - 0.5 * gr[0], js[1] / rs - 0.5 * gr[1], js[2] / rs - 0.5 * gr[2]};
+            const double phy = a.s0.phi[gid];
+            const bool yif = ty0 == F_IF;
+            const int cly = yif ? a.cls[gid] : 0;
+            const double lmty = a.lmt[gid];
+            double out[Q];
+            double lua[3] = {0.0, 0.0, 0.0};
+            double lphi = 0.0;
+            out[0] = a.lfin[pidx(a.g, b, 0, n)];
+#pragma unroll
+            for (int i = 1; i < Q; ++i) {
+                const int xn = nb_local(a.g, c.x, c.y, c.z, cx(i), cy(i), cz(i));   // y + c_i
+                const uint8_t tx = xn >= 0 ? a.s0.fl[cb + xn] : 0;
+                double v = 0.0;
+                if (xn < 0) {
+                    v = a.lfin[pidx(a.g, b, opp(i), n)];   // bounced back into y as opp(i)
+                } else if (tx == F_GAS) {
+                    // anti-bounce-back into y along opp(i) subtracts f*_i(y) and uses u(y)
+                    const int o = opp(i);
+                    const double l = a.lfin[pidx(a.g, b, o, n)];
+                    v = -l;
+                    const int co[3] = {cx(o), cy(o), cz(o)};
+                    const double uc = co[0] * ua[0] + co[1] * ua[1] + co[2] * ua[2];
+                    const double k2 = 2.0 * wgt<double>(o) * a.rhoG;
+                    for (int d = 0; d < 3; ++d) lua[d] += l * k2 * (9.0 * uc * co[d] - 3.0 * ua[d]);
+                } else {
+                    v = a.lfin[pidx(a.g, b, i, xn)];   // streamed into y + c_i
+                    const double fin_y = a.s0.f[pidx(a.g, b, opp(i), xn)];   // f*_opp(i)(y + c_i)
+                    const double fout_y = fs[i];                             // f*_i(y)
+                    const double phx = a.s0.phi[cb + xn];
+                    if (yif) {
+                        // link i of y carries fout = f*_i(y)
+                        if (tx == F_LIQ) {
+                            v -= lmty;
+                        } else {
+                            double ca, cbf;
+                            flux_coef(cly, a.cls[cb + xn], ca, cbf);
+                            v += lmty * 0.5 * (phy + phx) * cbf;
+                            lphi += lmty * 0.5 * (ca * fin_y + cbf * fout_y);
+                        }
+                    }
+                    if (tx == F_IF) {
+                        // link opp(i) of x = y + c_i carries fin = f*_i(y), fout = fin_y
+                        const double lmtx = a.lmt[cb + xn];
+                        if (!yif) {
+                            v += lmtx;
+                        } else {
+                            double ca, cbf;
+                            flux_coef(a.cls[cb + xn], cly, ca, cbf);
+                            v += lmtx * 0.5 * (phx + phy) * ca;
+                            lphi += lmtx * 0.5 * (ca * fout_y + cbf * fin_y);
+                        }
+                    }
+                }
+                out[i] = v;
+            }
+            if (lua[0] != 0.0 || lua[1] != 0.0 || lua[2] != 0.0) {
+                // u(y) = sum c f*(y) / rho*(y) - g/2
+#pragma unroll
+                for (int j = 0; j < Q; ++j) {
+                    const int cj[3] = {cx(j), cy(j), cz(j)};
+                    for (int d = 0; d < 3; ++d) out[j] += lua[d] * (cj[d] - (ua[d] + 0.5 * gr[d])) / rs;
+                }
+                for (int d = 0; d < 3; ++d) acc[1 + d] = -0.5 * lua[d];
+            }
+#pragma unroll
+            for (int i = 0; i < Q; ++i) a.lf0[pidx(a.g, b, i, n)] = out[i];
+            a.lm0[gid] = yif ? lmty : 0.0;
+            a.lphi0[gid] = yif ? lphi : 0.0;
+        }
+    }
+    block_add4(acc, a.gpart + ((long long)b * a.nblk + blockIdx.x) * 4);
+}
+
+// Interface height: h = sum of phi over the plane x = x_probe, one workgroup
+// per domain, fixed summation order.
+__global__ __launch_bounds__(BS) void k_height(Geom g, const double *phi, int x_probe, double *h,
+                                               long long stride, int t) {
+    const int b = blockIdx.x;
+    const long long plane = (long long)g.ny * g.nz;
+    double s = 0.0;
+    for (long long k = threadIdx.x; k < plane; k += BS) s += phi[(long long)b * g.N + k * g.nx + x_probe];
+    __shared__ double sh[BS];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = BS / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) h[(long long)b * stride + t] = sh[0];
+}
+
+__global__ __launch_bounds__(BS) void k_reduce_params(const double *gpart, int nblk, double *out) {
+    const int b = blockIdx.x;
+    __shared__ double sh[BS];
+    for (int k = 0; k < 4; ++k) {
+        double s = 0.0;
+        for (int j = threadIdx.x; j < nblk; j += BS) s += gpart[((long long)b * nblk + j) * 4 + k];
+        sh[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = BS / 2; w > 0; w >>= 1) {
+            if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[4 * b + k] = sh[0];
+        __syncthreads();
+    }
+}
+
+__global__ void k_save_scalars(const double *res, const int32_t *nif_dom, int B, int p_last, int p_cur,
+                               double *R, int32_t *nif, double *reservoir) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    R[b] = p_last >= 0 ? res[p_last * B + b] : 0.0;
+    nif[b] = p_last >= 0 ? nif_dom[p_last * B + b] : 0;
+    reservoir[b] = res[p_cur * B + b];
+}
+
+}  // namespace
+
+void launch_save_scalars(const double *res, const int32_t *nif_dom, int B, int p_last, int p_cur,
+                         double *R, int32_t *nif, double *reservoir, hipStream_t s) {
+    hipLaunchKernelGGL(k_save_scalars, dim3(unsigned((B + 255) / 256)), dim3(256), 0, s, res, nif_dom, B,
+                       p_last, p_cur, R, nif, reservoir);
+}
+
+void launch_adjoint_step(const AdjArgs &a, hipStream_t s) {
+    const dim3 grid(unsigned(a.nblk), unsigned(a.B));
+    hipLaunchKernelGGL(k_adj_classes, grid, dim3(BS), 0, s, a);
+    hipLaunchKernelGGL(k_adj_receivers, grid, dim3(BS), 0, s, a);
+    hipLaunchKernelGGL(k_adj_converted, grid, dim3(BS), 0, s, a);
+    hipLaunchKernelGGL(k_adj_refill, grid, dim3(BS), 0, s, a);
+    hipLaunchKernelGGL(k_adj_collide, grid, dim3(BS), 0, s, a);
+    hipLaunchKernelGGL(k_adj_stream, grid, dim3(BS), 0, s, a);
+}
+
+void launch_height(const Geom &g, int B, const double *phi, int x_probe, double *h, long long stride,
+                   int t, hipStream_t s) {
+    hipLaunchKernelGGL(k_height, dim3(unsigned(B)), dim3(BS), 0, s, g, phi, x_probe, h, stride, t);
+}
+
+void launch_reduce_params(const double *gpart, int B, int nblk, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_params, dim3(unsigned(B)), dim3(BS), 0, s, gpart, nblk, out);
+}
+
+}  // namespace fslbm

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/fslbm.h"
+#include "context.hpp"
 #include "fslbm_kernels.hpp"
 #include "fslbm_math.hpp"
 
@@ -21,17 +22,7 @@ namespace {
 
 constexpr int DIAG_BLOCKS = 256;
 
-size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
-
 size_t storage_bytes(int st) { return st == FSLBM_F64 ? 8 : (st == FSLBM_F32 ? 4 : 2); }
-
-// Byte offsets of every array inside the caller's workspace.
-struct Layout {
-    size_t pdf, fo, flags, m, phi, mex, rhoG, normal, band;
-    size_t lists[7];   // if0, if1, newg, froml, conv0, conv1, band
-    size_t cnt, nif, res, omega, grav, diag_d, diag_i;
-    size_t total;
-};
 
 bool make_layout(const fslbm_params &p, Layout &L) {
     long long N = (long long)p.nx * p.ny * p.nz;
@@ -299,25 +290,7 @@ __global__ __launch_bounds__(256) void k_diag_partial(StepArgs a, int layoutB, d
 
 // ------------------------------------------------------------------ context
 
-struct fslbm_ctx {
-    fslbm_params p{};
-    Layout L{};
-    char *ws = nullptr;
-    std::vector<double> omega_h, grav_h;
-    long long t = 0;                 // steps done
-    hipStream_t stream = nullptr;
-    hipStream_t cap_stream = nullptr;
-    SideStream side{nullptr, nullptr, nullptr};   // interface kernel beside the bulk kernel
-    bool graphs = true;
-    hipGraphExec_t exec[2] = {nullptr, nullptr};
-    fslbm_status status = FSLBM_OK;
-    std::string err = "no error";
-};
-
-namespace {
-
-template <typename T>
-T *at(fslbm_ctx *c, size_t off) { return reinterpret_cast<T *>(c->ws + off); }
+namespace fslbm {
 
 StepArgs make_args(fslbm_ctx *c, int parity) {
     StepArgs a{};
@@ -415,7 +388,77 @@ bool capture(fslbm_ctx *c, int parity) {
     return hip_ok(c, ie, "hipGraphInstantiate");
 }
 
-}  // namespace
+bool enqueue_step(fslbm_ctx *c) {
+    const int parity = int(c->t & 1);
+    if (c->graphs) {
+        if (!c->exec[parity] && !capture(c, parity)) return false;
+        if (!hip_ok(c, hipGraphLaunch(c->exec[parity], c->stream), "hipGraphLaunch")) return false;
+    } else {
+        launch_step(make_args(c, parity), c->p.storage, c->p.collision, c->p.refill, c->stream, c->side);
+        if (!hip_ok(c, hipGetLastError(), "step kernel launch")) return false;
+    }
+    ++c->t;
+    return true;
+}
+
+bool load_state(fslbm_ctx *c, const uint8_t *flags, const double *phi, const double *rho,
+                const double *u, const double *pdf, const double *mass, const double *reservoir) {
+    c->t = 0;
+    StepArgs a = make_args(c, 0);
+    const int B = c->p.batch;
+    const size_t sb = storage_bytes(c->p.storage);
+    bool ok = hip_ok(c, hipMemsetAsync(a.cnt, 0, C_COUNT * 4, c->stream), "hipMemset") &&
+              hip_ok(c, hipMemsetAsync(a.nif_dom, 0, 8 * B, c->stream), "hipMemset") &&
+              hip_ok(c, hipMemsetAsync(a.res, 0, 16 * B, c->stream), "hipMemset") &&
+              hip_ok(c, hipMemsetAsync(a.mex, 0, size_t(a.g.BN) * 8, c->stream), "hipMemset") &&
+              hip_ok(c, hipMemsetAsync(a.fo, 0, size_t(a.g.BN) * 18 * sb, c->stream), "hipMemset");
+    if (ok && a.band)
+        ok = hip_ok(c, hipMemsetAsync(a.band, 0, size_t((a.g.BN + 31) / 32) * 4, c->stream), "hipMemset") &&
+             hip_ok(c, hipMemsetAsync(a.rhoG, 0, size_t(a.g.BN) * 8, c->stream), "hipMemset") &&
+             hip_ok(c, hipMemsetAsync(a.normal, 0, size_t(a.g.BN) * 24, c->stream), "hipMemset");
+    // also clear the PDF array so gas slots hold finite values
+    ok = ok && hip_ok(c, hipMemsetAsync(a.pdf, 0, size_t(a.g.BN) * Q * sb, c->stream), "hipMemset(pdf)");
+    // the reservoir carried into the next step sits in the slot of parity 0
+    if (ok && reservoir)
+        ok = hip_ok(c, hipMemcpyAsync(a.res, reservoir, 8 * B, hipMemcpyDeviceToDevice, c->stream),
+                    "hipMemcpy(reservoir)");
+    if (!ok) return false;
+    InitArgs ia{a, flags, phi, rho, u, pdf, mass};
+    const unsigned nblk = unsigned((a.g.BN + 255) / 256);
+    switch (c->p.storage) {
+        case FSLBM_F64: hipLaunchKernelGGL(k_init_cells<ST_F64>, dim3(nblk), dim3(256), 0, c->stream, ia); break;
+        case FSLBM_F32: hipLaunchKernelGGL(k_init_cells<ST_F32>, dim3(nblk), dim3(256), 0, c->stream, ia); break;
+        case FSLBM_F16: hipLaunchKernelGGL(k_init_cells<ST_F16>, dim3(nblk), dim3(256), 0, c->stream, ia); break;
+        default: hipLaunchKernelGGL(k_init_cells<ST_BF16>, dim3(nblk), dim3(256), 0, c->stream, ia); break;
+    }
+    if (!hip_ok(c, hipGetLastError(), "k_init_cells")) return false;
+    hipLaunchKernelGGL(k_init_lists, dim3(nblk), dim3(256), 0, c->stream, a);
+    return hip_ok(c, hipGetLastError(), "k_init_lists");
+}
+
+bool enqueue_read(fslbm_ctx *c, uint32_t mask, void *const *dst) {
+    if (!mask) return true;
+    ReadArgs r{};
+    r.s = make_args(c, int(c->t & 1));
+    r.layoutB = int(c->t & 1);
+    r.mask = mask;
+    r.flags = static_cast<uint8_t *>(dst[0]);
+    r.pdf = static_cast<double *>(dst[1]);
+    r.mass = static_cast<double *>(dst[2]);
+    r.phi = static_cast<double *>(dst[3]);
+    r.rho = static_cast<double *>(dst[4]);
+    r.vel = static_cast<double *>(dst[5]);
+    const unsigned nblk = unsigned((r.s.g.BN + 255) / 256);
+    switch (c->p.storage) {
+        case FSLBM_F64: hipLaunchKernelGGL(k_read<ST_F64>, dim3(nblk), dim3(256), 0, c->stream, r); break;
+        case FSLBM_F32: hipLaunchKernelGGL(k_read<ST_F32>, dim3(nblk), dim3(256), 0, c->stream, r); break;
+        case FSLBM_F16: hipLaunchKernelGGL(k_read<ST_F16>, dim3(nblk), dim3(256), 0, c->stream, r); break;
+        default: hipLaunchKernelGGL(k_read<ST_BF16>, dim3(nblk), dim3(256), 0, c->stream, r); break;
+    }
+    return hip_ok(c, hipGetLastError(), "k_read");
+}
+
+}  // namespace fslbm
 
 // ------------------------------------------------------------------ C ABI
 
@@ -462,44 +505,14 @@ fslbm_status fslbm_init(const fslbm_params *params, void *workspace, size_t byte
         for (int k = 0; k < 3; ++k)
             c->grav_h[3 * b + k] = params->gravity_b ? params->gravity_b[3 * b + k] : params->gravity[k];
     }
-    StepArgs a = make_args(c, 0);
     bool ok = hip_ok(c, hipStreamCreateWithFlags(&c->side.stream, hipStreamNonBlocking), "hipStreamCreate") &&
               hip_ok(c, hipEventCreateWithFlags(&c->side.fork, hipEventDisableTiming), "hipEventCreate") &&
               hip_ok(c, hipEventCreateWithFlags(&c->side.join, hipEventDisableTiming), "hipEventCreate");
     ok = ok && hip_ok(c, hipMemcpyAsync(at<double>(c, c->L.omega), c->omega_h.data(), 8 * B,
                                        hipMemcpyHostToDevice, c->stream), "hipMemcpy(omega)") &&
               hip_ok(c, hipMemcpyAsync(at<double>(c, c->L.grav), c->grav_h.data(), 24 * B,
-                                       hipMemcpyHostToDevice, c->stream), "hipMemcpy(gravity)") &&
-              hip_ok(c, hipMemsetAsync(a.cnt, 0, C_COUNT * 4, c->stream), "hipMemset") &&
-              hip_ok(c, hipMemsetAsync(a.nif_dom, 0, 8 * B, c->stream), "hipMemset") &&
-              hip_ok(c, hipMemsetAsync(a.res, 0, 16 * B, c->stream), "hipMemset") &&
-              hip_ok(c, hipMemsetAsync(a.mex, 0, size_t(a.g.BN) * 8, c->stream), "hipMemset") &&
-              hip_ok(c, hipMemsetAsync(a.fo, 0, size_t(a.g.BN) * 18 * storage_bytes(c->p.storage), c->stream),
-                     "hipMemset");
-    if (ok && a.band)
-        ok = hip_ok(c, hipMemsetAsync(a.band, 0, size_t((a.g.BN + 31) / 32) * 4, c->stream), "hipMemset") &&
-             hip_ok(c, hipMemsetAsync(a.rhoG, 0, size_t(a.g.BN) * 8, c->stream), "hipMemset") &&
-             hip_ok(c, hipMemsetAsync(a.normal, 0, size_t(a.g.BN) * 24, c->stream), "hipMemset");
-    if (ok) {
-        // also clear the PDF array so gas slots hold finite values
-        ok = hip_ok(c, hipMemsetAsync(a.pdf, 0, size_t(a.g.BN) * Q * storage_bytes(c->p.storage), c->stream),
-                    "hipMemset(pdf)");
-    }
-    if (ok) {
-        InitArgs ia{a, flags, phi, rho, u, pdf, mass};
-        unsigned nblk = unsigned((a.g.BN + 255) / 256);
-        switch (c->p.storage) {
-            case FSLBM_F64: hipLaunchKernelGGL(k_init_cells<ST_F64>, dim3(nblk), dim3(256), 0, c->stream, ia); break;
-            case FSLBM_F32: hipLaunchKernelGGL(k_init_cells<ST_F32>, dim3(nblk), dim3(256), 0, c->stream, ia); break;
-            case FSLBM_F16: hipLaunchKernelGGL(k_init_cells<ST_F16>, dim3(nblk), dim3(256), 0, c->stream, ia); break;
-            default: hipLaunchKernelGGL(k_init_cells<ST_BF16>, dim3(nblk), dim3(256), 0, c->stream, ia); break;
-        }
-        ok = hip_ok(c, hipGetLastError(), "k_init_cells");
-        if (ok) {
-            hipLaunchKernelGGL(k_init_lists, dim3(nblk), dim3(256), 0, c->stream, a);
-            ok = hip_ok(c, hipGetLastError(), "k_init_lists");
-        }
-    }
+                                       hipMemcpyHostToDevice, c->stream), "hipMemcpy(gravity)");
+    ok = ok && load_state(c, flags, phi, rho, u, pdf, mass, nullptr);
     ok = ok && hip_ok(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize") && device_errors_ok(c);
     if (!ok) {
         g_init_error = c->err;
@@ -515,17 +528,8 @@ fslbm_status fslbm_step(fslbm_ctx *c, int32_t nsteps) {
     if (!c) return FSLBM_EINVAL;
     if (c->status != FSLBM_OK) return c->status;
     if (nsteps < 0) return fail(c, FSLBM_EINVAL, "nsteps must be >= 0");
-    for (int32_t s = 0; s < nsteps; ++s) {
-        int parity = int(c->t & 1);
-        if (c->graphs) {
-            if (!c->exec[parity] && !capture(c, parity)) return c->status;
-            if (!hip_ok(c, hipGraphLaunch(c->exec[parity], c->stream), "hipGraphLaunch")) return c->status;
-        } else {
-            launch_step(make_args(c, parity), c->p.storage, c->p.collision, c->p.refill, c->stream, c->side);
-            if (!hip_ok(c, hipGetLastError(), "step kernel launch")) return c->status;
-        }
-        ++c->t;
-    }
+    for (int32_t s = 0; s < nsteps; ++s)
+        if (!enqueue_step(c)) return c->status;
     return FSLBM_OK;
 }
 
@@ -598,26 +602,7 @@ fslbm_status fslbm_read_fields(fslbm_ctx *c, uint32_t mask, void *const *dst) {
     if (!dst && mask) return fail(c, FSLBM_EINVAL, "dst is NULL");
     for (int k = 0; k < 6; ++k)
         if ((mask >> k & 1u) && !dst[k]) return fail(c, FSLBM_EINVAL, "NULL destination for a requested field");
-    ReadArgs r{};
-    r.s = make_args(c, int(c->t & 1));
-    r.layoutB = int(c->t & 1);
-    r.mask = mask;
-    if (mask) {
-        r.flags = static_cast<uint8_t *>(dst[0]);
-        r.pdf = static_cast<double *>(dst[1]);
-        r.mass = static_cast<double *>(dst[2]);
-        r.phi = static_cast<double *>(dst[3]);
-        r.rho = static_cast<double *>(dst[4]);
-        r.vel = static_cast<double *>(dst[5]);
-        unsigned nblk = unsigned((r.s.g.BN + 255) / 256);
-        switch (c->p.storage) {
-            case FSLBM_F64: hipLaunchKernelGGL(k_read<ST_F64>, dim3(nblk), dim3(256), 0, c->stream, r); break;
-            case FSLBM_F32: hipLaunchKernelGGL(k_read<ST_F32>, dim3(nblk), dim3(256), 0, c->stream, r); break;
-            case FSLBM_F16: hipLaunchKernelGGL(k_read<ST_F16>, dim3(nblk), dim3(256), 0, c->stream, r); break;
-            default: hipLaunchKernelGGL(k_read<ST_BF16>, dim3(nblk), dim3(256), 0, c->stream, r); break;
-        }
-        if (!hip_ok(c, hipGetLastError(), "k_read")) return c->status;
-    }
+    if (!enqueue_read(c, mask, dst)) return c->status;
     if (!hip_ok(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize")) return c->status;
     if (!device_errors_ok(c)) return c->status;
     return FSLBM_OK;
@@ -641,12 +626,10 @@ fslbm_status fslbm_diagnostics(fslbm_ctx *c, fslbm_diag *out) {
     std::vector<double> hd(size_t(B) * DIAG_BLOCKS * 2);
     std::vector<long long> hi(size_t(B) * DIAG_BLOCKS * 4);
     std::vector<double> res(2 * B);
-    std::vector<int32_t> nif(2 * B);
     if (!hip_ok(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize") ||
         !hip_ok(c, hipMemcpy(hd.data(), pd, hd.size() * 8, hipMemcpyDeviceToHost), "hipMemcpy") ||
         !hip_ok(c, hipMemcpy(hi.data(), pi, hi.size() * 8, hipMemcpyDeviceToHost), "hipMemcpy") ||
-        !hip_ok(c, hipMemcpy(res.data(), a.res, 16 * B, hipMemcpyDeviceToHost), "hipMemcpy") ||
-        !hip_ok(c, hipMemcpy(nif.data(), a.nif_dom, 8 * B, hipMemcpyDeviceToHost), "hipMemcpy"))
+        !hip_ok(c, hipMemcpy(res.data(), a.res, 16 * B, hipMemcpyDeviceToHost), "hipMemcpy"))
         return c->status;
     if (!device_errors_ok(c)) return c->status;
     bool unstable = false;
@@ -661,11 +644,8 @@ fslbm_status fslbm_diagnostics(fslbm_ctx *c, fslbm_diag *out) {
             vmax = std::max(vmax, hd[2 * o + 1]);
             for (int j = 0; j < 4; ++j) cnt[j] += hi[4 * o + j];
         }
-        double r = 0.0;
-        if (c->t > 0) {
-            int p = int((c->t - 1) & 1);
-            r = nif[p * B + b] > 0 ? 0.0 : res[p * B + b];
-        }
+        // the reservoir carried into the next step (set at load, then by every step)
+        const double r = res[size_t(c->t & 1) * B + b];
         d.reservoir = r;
         d.total_mass = mass + r;
         d.max_speed = vmax;

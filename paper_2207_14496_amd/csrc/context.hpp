@@ -1,0 +1,78 @@
+// context.hpp -- the host-side library context shared by the C-ABI translation
+// units (forward step in api.hip, reverse mode in adjoint_api.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/fslbm.h"
+#include "fslbm_kernels.hpp"
+
+namespace fslbm {
+
+inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Byte offsets of every array inside the caller's workspace.
+struct Layout {
+    size_t pdf, fo, flags, m, phi, mex, rhoG, normal, band;
+    size_t lists[7];   // if0, if1, newg, froml, conv0, conv1, band
+    size_t cnt, nif, res, omega, grav, diag_d, diag_i;
+    size_t total;
+};
+
+// Bookkeeping of the last fslbm_adjoint_forward (what the backward sweep needs).
+struct AdjointRun {
+    bool valid = false;
+    const void *ws = nullptr;      // adjoint workspace it used
+    int T = 0, K = 0, S = 0, x_probe = 0;
+    const double *target = nullptr;
+};
+
+}  // namespace fslbm
+
+struct fslbm_ctx {
+    fslbm_params p{};
+    fslbm::Layout L{};
+    char *ws = nullptr;
+    std::vector<double> omega_h, grav_h;
+    long long t = 0;                 // steps done since the state was loaded
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    fslbm::SideStream side{nullptr, nullptr, nullptr};   // interface kernel beside the bulk kernel
+    bool graphs = true;
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    fslbm::AdjointRun adj;
+    fslbm_status status = FSLBM_OK;
+    std::string err = "no error";
+};
+
+namespace fslbm {
+
+template <typename T>
+T *at(fslbm_ctx *c, size_t off) { return reinterpret_cast<T *>(c->ws + off); }
+
+// Kernel arguments of a step with the given parity.
+StepArgs make_args(fslbm_ctx *c, int parity);
+
+// Record the first error (sticky) and return the context status.
+fslbm_status fail(fslbm_ctx *c, fslbm_status s, const std::string &msg);
+bool hip_ok(fslbm_ctx *c, hipError_t e, const char *what);
+// Check the device error word (the stream must be synchronised).
+bool device_errors_ok(fslbm_ctx *c);
+
+// Enqueue a full FSLBM step on the context's stream (graph replay or direct).
+bool enqueue_step(fslbm_ctx *c);
+
+// Load a canonical state (device arrays, layouts of fslbm_init) into the
+// context and restart its step count at 0.  reservoir: device [B] or null (0).
+// Enqueued on the context's stream; validation errors surface at the next
+// device_errors_ok.
+bool load_state(fslbm_ctx *c, const uint8_t *flags, const double *phi, const double *rho,
+                const double *u, const double *pdf, const double *mass, const double *reservoir);
+
+// Enqueue the canonical read-back of the fields in `mask` (no synchronisation).
+bool enqueue_read(fslbm_ctx *c, uint32_t mask, void *const *dst);
+
+}  // namespace fslbm

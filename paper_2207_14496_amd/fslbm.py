@@ -30,7 +30,8 @@ STORAGE_BYTES = {F64: 8, F32: 4, F16: 2, BF16: 2}
 SYMBOLS = ["fslbm_workspace_bytes", "fslbm_init", "fslbm_step", "fslbm_step_timed",
            "fslbm_refill_scheme",
            "fslbm_use_graphs", "fslbm_set_stream", "fslbm_read_fields", "fslbm_diagnostics",
-           "fslbm_last_step_stats", "fslbm_last_error", "fslbm_destroy"]
+           "fslbm_last_step_stats", "fslbm_adjoint_workspace_bytes", "fslbm_adjoint_forward",
+           "fslbm_adjoint_backward", "fslbm_last_error", "fslbm_destroy"]
 
 
 class FslbmError(RuntimeError):
@@ -65,6 +66,12 @@ class CStepStats(ctypes.Structure):
 _lib = None
 
 
+class CAdjSpec(ctypes.Structure):
+    _fields_ = [("nsteps", ctypes.c_int32), ("n_checkpoints", ctypes.c_int32),
+                ("x_probe", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("target", ctypes.c_void_p)]
+
+
 def lib() -> ctypes.CDLL:
     """Load libfslbm.so (raises if it is missing: there is no fallback)."""
     global _lib
@@ -85,6 +92,10 @@ def lib() -> ctypes.CDLL:
         L.fslbm_diagnostics.argtypes = [vp, P(CDiag)]
         L.fslbm_last_step_stats.argtypes = [vp, P(CStepStats)]
         L.fslbm_last_step_stats.restype = ctypes.c_int
+        L.fslbm_adjoint_workspace_bytes.argtypes = [vp, P(CAdjSpec), P(ctypes.c_size_t)]
+        L.fslbm_adjoint_forward.argtypes = [vp, P(CAdjSpec), vp, ctypes.c_size_t, vp, vp]
+        L.fslbm_adjoint_backward.argtypes = [vp, P(CAdjSpec), vp, ctypes.c_size_t, vp, vp, vp,
+                                             vp, vp, vp]
         L.fslbm_last_error.argtypes = [vp]
         L.fslbm_last_error.restype = ctypes.c_char_p
         L.fslbm_destroy.argtypes = [vp]
@@ -92,7 +103,8 @@ def lib() -> ctypes.CDLL:
         for name in ("fslbm_workspace_bytes", "fslbm_init", "fslbm_step", "fslbm_step_timed",
                      "fslbm_refill_scheme",
                      "fslbm_use_graphs", "fslbm_set_stream", "fslbm_read_fields",
-                     "fslbm_diagnostics"):
+                     "fslbm_diagnostics", "fslbm_adjoint_workspace_bytes",
+                     "fslbm_adjoint_forward", "fslbm_adjoint_backward"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -263,6 +275,62 @@ class Simulation:
         st = CStepStats()
         _check(lib().fslbm_last_step_stats(self._ctx, ctypes.byref(st)), self._ctx)
         return {k: getattr(st, k) for k, _ in CStepStats._fields_}
+
+    # ------------------------------------------------------------------ reverse mode
+    def adjoint_forward(self, target, nsteps: int, x_probe: int, n_checkpoints: int = 0):
+        """Run the loss window of ``nsteps`` steps from the current state with
+        checkpoints; ``target`` [B, nsteps] holds h*(t), t = 1..nsteps.  Returns
+        (loss [B], height [B, nsteps+1]) as float64 numpy arrays.  The state
+        advances to the end of the window."""
+        import numpy as np
+        B = self.params.batch
+        tgt = _dev(target, torch.float64, self.device).reshape(B, int(nsteps)).contiguous()
+        spec = CAdjSpec(int(nsteps), int(n_checkpoints), int(x_probe), 0, tgt.data_ptr())
+        nbytes = ctypes.c_size_t()
+        _check(lib().fslbm_adjoint_workspace_bytes(self._ctx, ctypes.byref(spec),
+                                                   ctypes.byref(nbytes)), self._ctx)
+        ws = getattr(self, "_adj_ws", None)
+        if ws is None or ws.numel() < nbytes.value + 256:
+            self._adj_ws = None
+            ws = self._adj_ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
+        wptr = (ws.data_ptr() + 255) & ~255
+        loss = np.zeros(B)
+        height = np.zeros((B, int(nsteps) + 1))
+        _check(lib().fslbm_adjoint_forward(self._ctx, ctypes.byref(spec), ctypes.c_void_p(wptr),
+                                           nbytes.value, loss.ctypes.data_as(ctypes.c_void_p),
+                                           height.ctypes.data_as(ctypes.c_void_p)), self._ctx)
+        self._adj = (spec, tgt, wptr, nbytes.value)
+        self.steps_done += int(nsteps)
+        return loss, height
+
+    def adjoint_backward(self, dloss=None, state_grads: bool = True) -> dict:
+        """Gradient of sum_b dloss[b] L_b for the last adjoint_forward window:
+        omega [B] and gravity [B, 3] (numpy), and, with ``state_grads``, the
+        start state's pdf [B, 19, N], mass [B, N] and phi [B, N] (device)."""
+        import numpy as np
+        if getattr(self, "_adj", None) is None:
+            raise FslbmError(EINVAL, "adjoint_backward needs a preceding adjoint_forward")
+        spec, _tgt, wptr, nbytes = self._adj
+        B, N = self.params.batch, self.params.N
+        dl = None
+        if dloss is not None:
+            dl = np.ascontiguousarray(np.asarray(dloss, dtype=np.float64).reshape(B))
+        gom = np.zeros(B)
+        gg = np.zeros((B, 3))
+        out = {}
+        ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+        if state_grads:
+            out["pdf"] = torch.empty((B, 19, N), dtype=torch.float64, device=self.device)
+            out["mass"] = torch.empty((B, N), dtype=torch.float64, device=self.device)
+            out["phi"] = torch.empty((B, N), dtype=torch.float64, device=self.device)
+        _check(lib().fslbm_adjoint_backward(
+            self._ctx, ctypes.byref(spec), ctypes.c_void_p(wptr), nbytes,
+            dl.ctypes.data_as(ctypes.c_void_p) if dl is not None else None,
+            gom.ctypes.data_as(ctypes.c_void_p), gg.ctypes.data_as(ctypes.c_void_p),
+            ptr(out.get("pdf")), ptr(out.get("mass")), ptr(out.get("phi"))), self._ctx)
+        out["omega"] = gom
+        out["gravity"] = gg
+        return out
 
     def close(self):
         if getattr(self, "_ctx", None):

@@ -334,3 +334,12 @@ def config(name: str, refill: int = 0) -> Setup:
     if name == "pool-wave":
         return pool_wave(refill=refill)
     raise KeyError(name)
+
+
+def target_perturbation(seed: int):
+    """Relative parameter perturbations (xi_omega, xi_g, xi_a0) of a seeded target
+    run of the differentiable standing wave: xi_omega ~ U(-0.01, 0.01),
+    xi_g, xi_a0 ~ U(-0.05, 0.05), drawn by numpy's PCG64 ``default_rng(seed)``."""
+    rng = np.random.default_rng(seed)
+    return (float(rng.uniform(-0.01, 0.01)), float(rng.uniform(-0.05, 0.05)),
+            float(rng.uniform(-0.05, 0.05)))
