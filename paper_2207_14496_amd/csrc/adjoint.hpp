@@ -57,8 +57,8 @@ void launch_height(const Geom &g, int B, const double *phi, int x_probe, double 
 void launch_reduce_params(const double *gpart, int B, int nblk, double *out, hipStream_t s);
 
 // Copy the per-domain scalars of the engine after a step into a state record:
-// R = res[p_last], nif = nif_dom[p_last], reservoir = res[p_cur]; with no step
-// done yet (p_last < 0) R and nif are zero.
+// R = res[p_last], nif = the interface count of that step (sharded counters),
+// reservoir = res[p_cur]; with no step done yet (p_last < 0) R and nif are zero.
 void launch_save_scalars(const double *res, const int32_t *nif_dom, int B, int p_last, int p_cur,
                          double *R, int32_t *nif, double *reservoir, hipStream_t s);
 

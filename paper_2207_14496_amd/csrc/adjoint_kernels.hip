@@ -519,7 +519,7 @@ __global__ void k_save_scalars(const double *res, const int32_t *nif_dom, int B,
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= B) return;
     R[b] = p_last >= 0 ? res[p_last * B + b] : 0.0;
-    nif[b] = p_last >= 0 ? nif_dom[p_last * B + b] : 0;
+    nif[b] = p_last >= 0 ? nif_sum(nif_dom, p_last, B, b) : 0;
     reservoir[b] = res[p_cur * B + b];
 }
 

@@ -39,14 +39,27 @@ bool make_layout(const fslbm_params &p, Layout &L) {
     L.rhoG = surf ? take(size_t(BN) * 8) : 0;
     L.normal = surf ? take(size_t(BN) * 24) : 0;
     L.band = surf ? take(size_t((BN + 31) / 32) * 4) : 0;
-    for (int k = 0; k < 7; ++k) L.lists[k] = (k == 6 && !surf) ? 0 : take(size_t(BN) * 4);
+    for (int k = 0; k < 5; ++k) L.lists[k] = take(size_t(BN) * 4);
+    // sharded lists: S slots of seg entries plus an overflow region of BN entries
+    L.sl_S = int32_t(std::max<long long>(1, std::min<long long>(256, BN / 1024)));
+    L.sl_seg = int32_t((BN + L.sl_S - 1) / L.sl_S);
+    L.sl_ovf = int32_t(BN);
+    for (int k = 0; k < 4; ++k) {
+        const bool need = k < 3 || surf;
+        L.sl_data[k] = need ? take((size_t(L.sl_S) * L.sl_seg + size_t(L.sl_ovf)) * 4) : 0;
+        L.sl_cnt[k] = need ? take(size_t(L.sl_S + 1) * 32 * 4) : 0;
+    }
+    L.claim = take(size_t(BN) + 4);
     L.cnt = take(C_COUNT * 4);
-    L.nif = take(size_t(2 * p.batch) * 4);
+    L.nif = take(size_t(2 * p.batch) * ND_SHARDS * 32 * 4);
     L.res = take(size_t(2 * p.batch) * 8);
     L.omega = take(size_t(p.batch) * 8);
     L.grav = take(size_t(p.batch) * 24);
     L.diag_d = take(size_t(p.batch) * DIAG_BLOCKS * 2 * 8);
     L.diag_i = take(size_t(p.batch) * DIAG_BLOCKS * 4 * 8);
+    const size_t ntiles = size_t((BN + 255) / 256);
+    L.tiles = take(ntiles * 4);
+    L.tile_bits = take((ntiles + 31) / 32 * 4);
     L.total = off;
     return true;
 }
@@ -154,7 +167,8 @@ __global__ void k_init_cells(InitArgs ia) {
     a.m[gid] = m;
 }
 
-// Forced filling/emptying classes and the first interface list.
+// Forced filling/emptying classes and the interface list of the step before the
+// first (read by the surface-tension kernels of the first step).
 __global__ void k_init_lists(StepArgs a) {
     long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     bool in = gid < a.g.BN;
@@ -171,9 +185,16 @@ __global__ void k_init_lists(StepArgs a) {
             has_gas |= fq == F_GAS;
         }
         a.flags[gid] = uint8_t(F_IF | (!has_liq ? F_NOFLUID : (!has_gas ? F_NOEMPTY : 0)));
-        atomicAdd(a.nif_dom + a.B + int(gid / a.g.N), 1);
     }
-    wave_append(is_if, int32_t(gid), a.list_old, a.cnt + C_IF0, a.cap, a.cnt + C_ERR);
+    slist_append(a.list_if_prev, is_if, int32_t(gid), a.cnt + C_ERR);
+}
+
+// The tiles (256 consecutive cells) that hold liquid or interface cells.
+__global__ __launch_bounds__(256) void k_init_tiles(StepArgs a) {
+    const long long gid = (long long)blockIdx.x * 256 + threadIdx.x;
+    const bool fluid = gid < a.g.BN && (a.flags[gid] & (F_LIQ | F_IF));
+    if (__syncthreads_or(fluid) && threadIdx.x == 0)
+        activate_tile(a.tiles, a.tile_bits, a.cnt + C_TILES, int32_t(blockIdx.x), int32_t(gridDim.x));
 }
 
 // ------------------------------------------------------------------ read-back
@@ -320,15 +341,29 @@ StepArgs make_args(fslbm_ctx *c, int parity) {
     a.sigma = p.sigma;
     a.p_volume = p.p_volume;
     a.eps_phi = p.eps_phi;
-    int32_t *lists[7];
-    for (int k = 0; k < 7; ++k) lists[k] = c->L.lists[k] ? at<int32_t>(c, c->L.lists[k]) : nullptr;
-    a.list_old = lists[parity];
-    a.list_new = lists[1 - parity];
-    a.list_newg = lists[2];
-    a.list_froml = lists[3];
-    a.list_conv = lists[4 + parity];
-    a.list_conv_prev = lists[4 + (1 - parity)];
-    a.list_band = lists[6];
+    int32_t *lists[5];
+    for (int k = 0; k < 5; ++k) lists[k] = at<int32_t>(c, c->L.lists[k]);
+    a.list_newg = lists[0];
+    a.list_froml = lists[1];
+    a.list_conv = lists[2 + parity];
+    a.list_conv_prev = lists[2 + (1 - parity)];
+    a.list_recv = lists[4];
+    SList sl[4];
+    for (int k = 0; k < 4; ++k) {
+        sl[k].data = c->L.sl_data[k] ? at<int32_t>(c, c->L.sl_data[k]) : nullptr;
+        sl[k].cnt = c->L.sl_cnt[k] ? at<int32_t>(c, c->L.sl_cnt[k]) : nullptr;
+        sl[k].S = c->L.sl_S;
+        sl[k].seg = c->L.sl_seg;
+        sl[k].ovf = c->L.sl_ovf;
+    }
+    a.list_if = sl[parity];
+    a.list_if_prev = sl[1 - parity];
+    a.list_mark = sl[2];
+    a.list_band = sl[3];
+    a.claim = at<uint8_t>(c, c->L.claim);
+    a.tiles = at<int32_t>(c, c->L.tiles);
+    a.tile_bits = at<uint32_t>(c, c->L.tile_bits);
+    a.bulk_grid = c->bulk_grid;
     a.cnt = at<int32_t>(c, c->L.cnt);
     a.nif_dom = at<int32_t>(c, c->L.nif);
     a.res = at<double>(c, c->L.res);
@@ -379,7 +414,7 @@ bool capture(fslbm_ctx *c, int parity) {
     if (!hip_ok(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal),
                 "hipStreamBeginCapture"))
         return false;
-    launch_step(make_args(c, parity), c->p.storage, c->p.collision, c->p.refill, c->cap_stream, c->side);
+    launch_step(make_args(c, parity), c->p.storage, c->p.collision, c->p.refill, c->cap_stream);
     hipError_t le = hipGetLastError();
     hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
     if (!hip_ok(c, le, "kernel launch (capture)") || !hip_ok(c, e, "hipStreamEndCapture")) return false;
@@ -394,7 +429,7 @@ bool enqueue_step(fslbm_ctx *c) {
         if (!c->exec[parity] && !capture(c, parity)) return false;
         if (!hip_ok(c, hipGraphLaunch(c->exec[parity], c->stream), "hipGraphLaunch")) return false;
     } else {
-        launch_step(make_args(c, parity), c->p.storage, c->p.collision, c->p.refill, c->stream, c->side);
+        launch_step(make_args(c, parity), c->p.storage, c->p.collision, c->p.refill, c->stream);
         if (!hip_ok(c, hipGetLastError(), "step kernel launch")) return false;
     }
     ++c->t;
@@ -408,10 +443,18 @@ bool load_state(fslbm_ctx *c, const uint8_t *flags, const double *phi, const dou
     const int B = c->p.batch;
     const size_t sb = storage_bytes(c->p.storage);
     bool ok = hip_ok(c, hipMemsetAsync(a.cnt, 0, C_COUNT * 4, c->stream), "hipMemset") &&
-              hip_ok(c, hipMemsetAsync(a.nif_dom, 0, 8 * B, c->stream), "hipMemset") &&
+              hip_ok(c, hipMemsetAsync(a.nif_dom, 0, size_t(2 * B) * ND_SHARDS * 32 * 4, c->stream),
+                     "hipMemset") &&
               hip_ok(c, hipMemsetAsync(a.res, 0, 16 * B, c->stream), "hipMemset") &&
               hip_ok(c, hipMemsetAsync(a.mex, 0, size_t(a.g.BN) * 8, c->stream), "hipMemset") &&
-              hip_ok(c, hipMemsetAsync(a.fo, 0, size_t(a.g.BN) * 18 * sb, c->stream), "hipMemset");
+              hip_ok(c, hipMemsetAsync(a.fo, 0, size_t(a.g.BN) * 18 * sb, c->stream), "hipMemset") &&
+              hip_ok(c, hipMemsetAsync(a.tile_bits, 0, size_t((a.g.BN + 255) / 256 + 31) / 32 * 4, c->stream),
+                     "hipMemset") &&
+              hip_ok(c, hipMemsetAsync(a.claim, 0, size_t(a.g.BN) + 4, c->stream), "hipMemset");
+    for (int k = 0; ok && k < 4; ++k)
+        if (c->L.sl_cnt[k])
+            ok = hip_ok(c, hipMemsetAsync(at<int32_t>(c, c->L.sl_cnt[k]), 0, size_t(c->L.sl_S + 1) * 32 * 4,
+                                          c->stream), "hipMemset");
     if (ok && a.band)
         ok = hip_ok(c, hipMemsetAsync(a.band, 0, size_t((a.g.BN + 31) / 32) * 4, c->stream), "hipMemset") &&
              hip_ok(c, hipMemsetAsync(a.rhoG, 0, size_t(a.g.BN) * 8, c->stream), "hipMemset") &&
@@ -433,7 +476,23 @@ bool load_state(fslbm_ctx *c, const uint8_t *flags, const double *phi, const dou
     }
     if (!hip_ok(c, hipGetLastError(), "k_init_cells")) return false;
     hipLaunchKernelGGL(k_init_lists, dim3(nblk), dim3(256), 0, c->stream, a);
-    return hip_ok(c, hipGetLastError(), "k_init_lists");
+    if (!hip_ok(c, hipGetLastError(), "k_init_lists")) return false;
+    hipLaunchKernelGGL(k_init_tiles, dim3(nblk), dim3(256), 0, c->stream, a);
+    return hip_ok(c, hipGetLastError(), "k_init_tiles");
+}
+
+bool refresh_bulk_grid(fslbm_ctx *c) {
+    int32_t n = 0;
+    if (!hip_ok(c, hipMemcpy(&n, at<int32_t>(c, c->L.cnt) + C_TILES, 4, hipMemcpyDeviceToHost),
+                "hipMemcpy(tile count)"))
+        return false;
+    const long long total = ((long long)c->p.nx * c->p.ny * c->p.nz * c->p.batch + 255) / 256;
+    const long long want = std::min<long long>(total, std::max<long long>(1024, 2LL * n));
+    if (want > c->bulk_grid) {
+        c->bulk_grid = int(want);
+        drop_graphs(c);
+    }
+    return true;
 }
 
 bool enqueue_read(fslbm_ctx *c, uint32_t mask, void *const *dst) {
@@ -505,15 +564,13 @@ fslbm_status fslbm_init(const fslbm_params *params, void *workspace, size_t byte
         for (int k = 0; k < 3; ++k)
             c->grav_h[3 * b + k] = params->gravity_b ? params->gravity_b[3 * b + k] : params->gravity[k];
     }
-    bool ok = hip_ok(c, hipStreamCreateWithFlags(&c->side.stream, hipStreamNonBlocking), "hipStreamCreate") &&
-              hip_ok(c, hipEventCreateWithFlags(&c->side.fork, hipEventDisableTiming), "hipEventCreate") &&
-              hip_ok(c, hipEventCreateWithFlags(&c->side.join, hipEventDisableTiming), "hipEventCreate");
-    ok = ok && hip_ok(c, hipMemcpyAsync(at<double>(c, c->L.omega), c->omega_h.data(), 8 * B,
+    bool ok = hip_ok(c, hipMemcpyAsync(at<double>(c, c->L.omega), c->omega_h.data(), 8 * B,
                                        hipMemcpyHostToDevice, c->stream), "hipMemcpy(omega)") &&
               hip_ok(c, hipMemcpyAsync(at<double>(c, c->L.grav), c->grav_h.data(), 24 * B,
                                        hipMemcpyHostToDevice, c->stream), "hipMemcpy(gravity)");
     ok = ok && load_state(c, flags, phi, rho, u, pdf, mass, nullptr);
-    ok = ok && hip_ok(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize") && device_errors_ok(c);
+    ok = ok && hip_ok(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize") && device_errors_ok(c) &&
+         refresh_bulk_grid(c);
     if (!ok) {
         g_init_error = c->err;
         fslbm_status s = c->status;
@@ -545,7 +602,7 @@ fslbm_status fslbm_step_timed(fslbm_ctx *c, int32_t nsteps, double *bulk_ms, dou
     for (int32_t s = 0; ok && s < nsteps; ++s) {
         BulkEvents be{ev[2 * s], ev[2 * s + 1]};
         launch_step(make_args(c, int(c->t & 1)), c->p.storage, c->p.collision, c->p.refill, c->stream,
-                    c->side, &be);
+                    &be);
         ok = hip_ok(c, hipGetLastError(), "step kernel launch");
         if (ok) ++c->t;
     }
@@ -604,7 +661,7 @@ fslbm_status fslbm_read_fields(fslbm_ctx *c, uint32_t mask, void *const *dst) {
         if ((mask >> k & 1u) && !dst[k]) return fail(c, FSLBM_EINVAL, "NULL destination for a requested field");
     if (!enqueue_read(c, mask, dst)) return c->status;
     if (!hip_ok(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize")) return c->status;
-    if (!device_errors_ok(c)) return c->status;
+    if (!device_errors_ok(c) || !refresh_bulk_grid(c)) return c->status;
     return FSLBM_OK;
 }
 
@@ -631,7 +688,7 @@ fslbm_status fslbm_diagnostics(fslbm_ctx *c, fslbm_diag *out) {
         !hip_ok(c, hipMemcpy(hi.data(), pi, hi.size() * 8, hipMemcpyDeviceToHost), "hipMemcpy") ||
         !hip_ok(c, hipMemcpy(res.data(), a.res, 16 * B, hipMemcpyDeviceToHost), "hipMemcpy"))
         return c->status;
-    if (!device_errors_ok(c)) return c->status;
+    if (!device_errors_ok(c) || !refresh_bulk_grid(c)) return c->status;
     bool unstable = false;
     const double cs = 1.0 / std::sqrt(3.0);
     for (int b = 0; b < B; ++b) {
@@ -669,12 +726,13 @@ fslbm_status fslbm_last_step_stats(fslbm_ctx *c, fslbm_step_stats *out) {
                 "hipMemcpy(counters)"))
         return c->status;
     *out = fslbm_step_stats{};
-    if (c->t == 0) {
-        out->interface_cells = cnt[C_IF0];
-        return FSLBM_OK;
-    }
+    if (c->t == 0) return FSLBM_OK;
     const int p = int((c->t - 1) & 1);   // parity of the last step
-    out->interface_cells = cnt[C_IF0 + (1 - p)];
+    std::vector<int32_t> nif(size_t(c->p.batch) * ND_SHARDS * 32);
+    if (!hip_ok(c, hipMemcpy(nif.data(), at<int32_t>(c, c->L.nif) + size_t(p) * nif.size(),
+                             4 * nif.size(), hipMemcpyDeviceToHost), "hipMemcpy(interface counts)"))
+        return c->status;
+    for (size_t k = 0; k < nif.size(); k += 32) out->interface_cells += nif[k];
     out->new_from_gas = cnt[C_NEWG];
     out->from_liquid = cnt[C_FROML];
     out->converted = cnt[C_CONV0 + p];
@@ -689,9 +747,6 @@ void fslbm_destroy(fslbm_ctx *c) {
     if (!c) return;
     drop_graphs(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-    if (c->side.stream) (void)hipStreamDestroy(c->side.stream);
-    if (c->side.fork) (void)hipEventDestroy(c->side.fork);
-    if (c->side.join) (void)hipEventDestroy(c->side.join);
     delete c;
 }
 

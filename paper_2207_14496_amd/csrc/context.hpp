@@ -17,8 +17,12 @@ inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 // Byte offsets of every array inside the caller's workspace.
 struct Layout {
     size_t pdf, fo, flags, m, phi, mex, rhoG, normal, band;
-    size_t lists[7];   // if0, if1, newg, froml, conv0, conv1, band
+    size_t lists[5];   // newg, froml, conv0, conv1, recv
+    size_t sl_data[4], sl_cnt[4];   // sharded lists: interface (even / odd step), marks, band
+    int32_t sl_S, sl_seg, sl_ovf;
+    size_t claim;
     size_t cnt, nif, res, omega, grav, diag_d, diag_i;
+    size_t tiles, tile_bits;
     size_t total;
 };
 
@@ -40,9 +44,9 @@ struct fslbm_ctx {
     long long t = 0;                 // steps done since the state was loaded
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
-    fslbm::SideStream side{nullptr, nullptr, nullptr};   // interface kernel beside the bulk kernel
     bool graphs = true;
     hipGraphExec_t exec[2] = {nullptr, nullptr};
+    int bulk_grid = 1024;            // workgroups of the bulk kernel (tile-list stride)
     fslbm::AdjointRun adj;
     fslbm_status status = FSLBM_OK;
     std::string err = "no error";
@@ -71,6 +75,11 @@ bool enqueue_step(fslbm_ctx *c);
 // device_errors_ok.
 bool load_state(fslbm_ctx *c, const uint8_t *flags, const double *phi, const double *rho,
                 const double *u, const double *pdf, const double *mass, const double *reservoir);
+
+// Grow the bulk kernel's grid to twice the fluid-tile count (capped by the
+// tile total) if the list has outgrown it.  Needs a synchronised stream; drops
+// the captured graphs when the grid changes.
+bool refresh_bulk_grid(fslbm_ctx *c);
 
 // Enqueue the canonical read-back of the fields in `mask` (no synchronisation).
 bool enqueue_read(fslbm_ctx *c, uint32_t mask, void *const *dst);

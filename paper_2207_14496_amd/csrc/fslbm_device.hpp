@@ -177,6 +177,25 @@ __device__ __forceinline__ long long slot_flat(const Geom &g, int layoutB, const
     return base + (long long)opp(i) * g.N + c.n;
 }
 
+// ------------------------------------------------------------------ lists
+// Append-only int32 list whose length is split over S counters, one 128-byte
+// line each.  On MI355X atomics on a single address serialise (about 11 ns
+// each), so thousands of wavefronts appending to one counter would take
+// hundreds of microseconds; here wavefront w appends to slot w mod S, which
+// owns a segment of `seg` entries.  Entries that do not fit their segment go
+// to a shared overflow region, so the list holds S * seg + ovf entries in any
+// distribution.  Slot s's length is cnt[32 s] (clamped to seg when read); the
+// overflow length is cnt[32 S].
+struct SList {
+    int32_t *data;     // [S * seg + ovf]
+    int32_t *cnt;      // [(S + 1) * 32]
+    int32_t S, seg, ovf;
+};
+
+// Interface cells per domain, split over ND_SHARDS counters per domain (one
+// 128-byte line each): [2 parities][B][ND_SHARDS][32].
+constexpr int ND_SHARDS = 64;
+
 // ------------------------------------------------------------------ arguments
 struct StepArgs {
     Geom g;
@@ -195,10 +214,19 @@ struct StepArgs {
     const double *grav;    // [B][3]
     double trt_lambda;
     double sigma, p_volume, eps_phi;
-    int32_t *list_old, *list_new;   // interface lists (this step / next step)
-    int32_t *list_newg, *list_froml, *list_conv, *list_conv_prev, *list_band;
+    SList list_if;          // interface cells of this step, built by the bulk kernel in tile order
+    SList list_if_prev;     // the same list of the last step
+    SList list_mark;        // interface cells marked for filling or emptying this step
+    SList list_band;        // surface band (sigma != 0)
+    int32_t *list_newg, *list_froml, *list_conv, *list_conv_prev;
+    int32_t *list_recv;     // interface cells that receive excess mass this step
+    uint8_t *claim;         // [BN] receiver claim bytes, zero between steps
+    int32_t *tiles;        // tiles (256 consecutive cells) that ever held fluid
+    uint32_t *tile_bits;   // membership bits of that list
+    int bulk_grid;         // workgroups of the bulk kernel (it strides over the tiles)
     int32_t *cnt;          // device counters, see Counter
-    int32_t *nif_dom;      // [2][B] interface cells per domain after conversion
+    int32_t *nif_dom;      // sharded interface cells per domain (see ND_SHARDS): counted by
+                           // the interface kernel, then corrected by the step's conversions
     double *res;           // [2][B] reservoir of excess mass
     int parity;            // step parity: 0 = layout A -> B, 1 = layout B -> A
     int B;
@@ -207,12 +235,12 @@ struct StepArgs {
 
 // Counter slots in StepArgs::cnt.  Index by parity where noted.
 enum Counter {
-    C_IF0 = 0, C_IF1 = 1,        // interface list sizes (list 0 / list 1)
     C_NEWG = 2, C_FROML = 3,     // this step's conversion lists
     C_CONV0 = 4, C_CONV1 = 5,    // converted interface cells (by step parity)
-    C_BAND = 6,
     C_ERR = 7,                   // sticky device error bits
-    C_COUNT = 8
+    C_TILES = 8,                 // length of the tile list
+    C_RECV = 10,                 // excess-mass receivers
+    C_COUNT = 11
 };
 enum DeviceError { E_LIST_OVERFLOW = 1, E_OPEN_LAYER = 2, E_BAD_FLAG = 4, E_BAD_PHI = 8 };
 
@@ -232,6 +260,130 @@ __device__ __forceinline__ void wave_append(bool pred, int32_t v, int32_t *list,
         if (pos < cap) list[pos] = v;
         else atomicOr(err, E_LIST_OVERFLOW);
     }
+}
+
+// ------------------------------------------------------------------ sharded lists
+
+// Zero the counters of a sharded list (all threads of one workgroup).
+__device__ __forceinline__ void slist_reset(const SList &L) {
+    for (int t = threadIdx.x; t <= L.S; t += blockDim.x) L.cnt[32 * t] = 0;
+}
+
+// Append the entries val(i) of every lane whose bit i is set in sel (i < NI),
+// one reservation per wavefront on the wavefront's slot.  Must be called by
+// all lanes of the wavefront that are active in the enclosing loop.
+template <int NI, typename V>
+__device__ __forceinline__ void slist_append_sel(const SList &L, uint32_t sel, V val, int32_t *err) {
+    unsigned long long masks[NI];
+    int pre[NI];
+    int tot = 0;
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        masks[i] = __ballot((sel >> i) & 1u);
+        pre[i] = tot;
+        tot += __popcll(masks[i]);
+    }
+    if (tot == 0) return;
+    const unsigned long long active = __ballot(1);
+    const int lane = __lane_id();
+    const int leader = __ffsll((long long)active) - 1;
+    const int slot = int(((blockIdx.x * blockDim.x + threadIdx.x) >> 6) % unsigned(L.S));
+    int base = 0, obase = 0;
+    if (lane == leader) {
+        base = atomicAdd(L.cnt + 32 * slot, tot);
+        const int spill = base + tot - (base > L.seg ? base : L.seg);
+        if (spill > 0) obase = atomicAdd(L.cnt + 32 * L.S, spill);
+    }
+    base = __shfl(base, leader);
+    obase = __shfl(obase, leader);
+    const int first_spill = base > L.seg ? base : L.seg;   // first position past the segment
+    const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        if ((sel >> i) & 1u) {
+            const int pos = base + pre[i] + __popcll(masks[i] & below);
+            if (pos < L.seg) {
+                L.data[(long long)slot * L.seg + pos] = val(i);
+            } else {
+                const int o = obase + (pos - first_spill);
+                if (o < L.ovf) L.data[(long long)L.S * L.seg + o] = val(i);
+                else atomicOr(err, E_LIST_OVERFLOW);
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void slist_append(const SList &L, bool pred, int32_t v, int32_t *err) {
+    slist_append_sel<1>(L, pred ? 1u : 0u, [&](int) { return v; }, err);
+}
+
+// Read side: prefix sums of the clamped slot lengths in shared memory (every
+// thread of the workgroup calls slist_view; blockDim.x == 256 >= S).
+struct SView {
+    const int32_t *data;
+    const int32_t *pref;   // [S + 1] in shared memory
+    int32_t S, seg;
+    long long nseg, total;
+};
+
+__device__ __forceinline__ SView slist_view(const SList &L, int32_t *pref) {
+    const int t = threadIdx.x;
+    int v = 0;
+    if (t < L.S) {
+        v = L.cnt[32 * t];
+        v = v < L.seg ? v : L.seg;
+    }
+    pref[t + 1] = v;
+    if (t == 0) pref[0] = 0;
+    __syncthreads();
+    // inclusive scan of pref[1..256] (Hillis-Steele)
+    for (int off = 1; off < 256; off <<= 1) {
+        const int add = (t + 1 - off >= 1) ? pref[t + 1 - off] : 0;
+        __syncthreads();
+        pref[t + 1] += add;
+        __syncthreads();
+    }
+    SView w;
+    w.data = L.data;
+    w.pref = pref;
+    w.S = L.S;
+    w.seg = L.seg;
+    w.nseg = pref[L.S];
+    int o = L.cnt[32 * L.S];
+    o = o < L.ovf ? o : L.ovf;
+    w.total = w.nseg + o;
+    return w;
+}
+
+// Entry k < total of the list.
+__device__ __forceinline__ int32_t sview_at(const SView &w, long long k) {
+    if (k >= w.nseg) return w.data[(long long)w.S * w.seg + (k - w.nseg)];
+    int lo = 0, hi = w.S;   // pref[lo] <= k < pref[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (w.pref[mid] <= k) lo = mid;
+        else hi = mid;
+    }
+    return w.data[(long long)lo * w.seg + (k - w.pref[lo])];
+}
+
+// Sharded per-domain interface counts.
+__device__ __forceinline__ int32_t *nif_slot(int32_t *nif, int p, int B, int b, int shard) {
+    return nif + (((long long)p * B + b) * ND_SHARDS + shard) * 32;
+}
+__device__ __forceinline__ int32_t nif_sum(const int32_t *nif, int p, int B, int b) {
+    int32_t s = 0;
+    for (int k = 0; k < ND_SHARDS; ++k) s += nif[(((long long)p * B + b) * ND_SHARDS + k) * 32];
+    return s;
+}
+
+// Add tile t to the fluid-tile list unless it is there already.
+__device__ __forceinline__ void activate_tile(int32_t *tiles, uint32_t *bits, int32_t *count, int32_t t,
+                                              int32_t ntiles) {
+    const uint32_t bit = 1u << (t & 31);
+    if (atomicOr(bits + (t >> 5), bit) & bit) return;
+    const int32_t pos = atomicAdd(count, 1);
+    if (pos < ntiles) tiles[pos] = t;
 }
 
 // Byte-granular atomic OR on the flag array (4-byte aligned, padded).

@@ -11,20 +11,13 @@ struct BulkEvents {
     hipEvent_t before, after;
 };
 
-// Second stream (default priority) and the two events that fork the
-// interface-cell kernel off the main stream and join it back.
-struct SideStream {
-    hipStream_t stream;
-    hipEvent_t fork, join;
-};
-
 // Enqueue one full FSLBM step (all sub-steps) with the given arguments.
 void launch_step(const StepArgs &a, int storage, int collision, int scheme, hipStream_t s,
-                 const SideStream &side, const BulkEvents *ev = nullptr);
+                 const BulkEvents *ev = nullptr);
 
 // The same for one PDF storage type (one translation unit per type).
 template <int ST>
 void launch_step_storage(const StepArgs &a, int collision, int scheme, hipStream_t s,
-                         const BulkEvents *ev, const SideStream &side);
+                         const BulkEvents *ev);
 
 }  // namespace fslbm

@@ -1,19 +1,21 @@
 // step_kernels.hip -- the kernels of one FSLBM time step on gfx950.
 //
 // Per step (parity p = steps done mod 2; layout A before even steps, B before
-// odd ones, see fslbm_device.hpp), four kernels plus three for surface tension:
+// odd ones, see fslbm_device.hpp), five kernels plus three for surface tension:
 //   [sigma != 0]  k_band -> k_normals -> k_curvature    (Sec. 2.2, curvature)
-//   k_stream_collide  liquid cells: in-place stream + bounce-back + collide
-//   k_interface       (concurrently, second stream) interface cells: the same
-//                     plus the mass exchange (Sec. 2.2 mass flux with the
-//                     forced filling/emptying table), the anti-bounce-back
-//                     condition, phi = m/rho and the conversion marks
-//   k_resolve         interface list: conflict rules -> new / from-liquid lists
+//   k_stream_collide  fluid tiles: liquid cells get the in-place stream +
+//                     bounce-back + collide; interface cells get their forced
+//                     filling/emptying class and are listed in tile order
+//   k_interface       interface list: the same update plus the mass exchange
+//                     (Sec. 2.2 mass flux with the forced filling/emptying
+//                     table), the anti-bounce-back condition, phi = m/rho and
+//                     the conversion marks; marked cells are listed
+//   k_resolve         marked cells: conflict rules -> new / from-liquid lists
 //   k_convert         new cells: refilling (Sec. 3.1), 32 lanes per cell;
-//                     interface cells: conversions, excess mass and receiver
-//                     counts (Sec. 2.2); the next interface list
-//   k_excess          next interface list: gather excess shares and the
-//                     reservoir, phi, forced classes; bookkeeping for the next step
+//                     marked cells: conversions, excess mass, receivers
+//                     (Sec. 2.2); from-liquid cells
+//   k_excess          receivers: gather excess shares (and the reservoir);
+//                     phi; bookkeeping for the next step
 // Only the bulk kernel touches every cell; the others walk compacted int32
 // lists whose lengths live in device memory, so the whole sequence can be
 // captured once and replayed as a HIP graph.
@@ -173,13 +175,33 @@ __device__ __forceinline__ double feq_shift_rt(int i, double rho, double ux, dou
 
 // ------------------------------------------------------------------ surface
 
+// The interface cells at the start of the step, before the bulk kernel lists
+// them: the last step's list entries that are still interface, then the last
+// step's new and from-liquid cells.  Item k of n0 + n1 + n2; false if the entry
+// is no longer an interface cell.
+__device__ __forceinline__ bool start_interface(const StepArgs &a, const SView &prev, long long k,
+                                                long long n0, long long n1, long long &gid) {
+    if (k < n0) {
+        gid = sview_at(prev, k);
+        return (a.flags[gid] & F_TYPE) == F_IF;
+    }
+    gid = k - n0 < n1 ? a.list_newg[k - n0] : a.list_froml[k - n0 - n1];
+    return true;
+}
+#define START_COUNTS                                                                   \
+    __shared__ int32_t pref_[257];                                                     \
+    const SView prev = slist_view(a.list_if_prev, pref_);                              \
+    const long long n0 = prev.total, n1 = clamp_cap(a, a.cnt[C_NEWG]),                 \
+                    n2 = clamp_cap(a, a.cnt[C_FROML])
+
 // Mark the band (interface cells and their 3x3x3 neighbours) once and list it.
 __global__ __launch_bounds__(256) void k_band(StepArgs a) {
-    FOR_UNIFORM(k, in, clamp_cap(a, a.cnt[C_IF0 + a.parity])) {
+    START_COUNTS;
+    FOR_UNIFORM(k, in, n0 + n1 + n2) {
         uint32_t sel = 0;
         long long cells[27];
-        if (in) {
-            const long long gid = a.list_old[k];
+        long long gid = 0;
+        if (in && start_interface(a, prev, k, n0, n1, gid)) {
             const Cell c = decode(a.g, gid);
             const long long base = (long long)c.b * a.g.N;
             unsigned int olds[27], bits[27];
@@ -193,16 +215,18 @@ __global__ __launch_bounds__(256) void k_band(StepArgs a) {
 #pragma unroll
             for (int j = 0; j < 27; ++j) sel |= (olds[j] & bits[j]) ? 0u : (1u << j);
         }
-        wave_append_sel<27>(sel, [&](int j) { return int32_t(cells[j]); }, a.list_band,
-                            a.cnt + C_BAND, a.cap, a.cnt + C_ERR);
+        slist_append_sel<27>(a.list_band, sel, [&](int j) { return int32_t(cells[j]); }, a.cnt + C_ERR);
     }
 }
 
 // Unit normal n^ = grad(phi)/|grad(phi)| on the band (Parker-Youngs), phi(t).
 __global__ __launch_bounds__(256) void k_normals(StepArgs a) {
     const long long BN = a.g.BN;
-    FOR_LIST(k, a.cnt[C_BAND]) {
-        const long long gid = a.list_band[k];
+    __shared__ int32_t pref[257];
+    const SView band = slist_view(a.list_band, pref);
+    for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < band.total;
+         k += (long long)gridDim.x * blockDim.x) {
+        const long long gid = sview_at(band, k);
         const Cell c = decode(a.g, gid);
         double gx, gy, gz;
         py_gradient(a.g, c, [&](long long q) { return a.phi_cur[q]; }, gx, gy, gz);
@@ -217,8 +241,11 @@ __global__ __launch_bounds__(256) void k_normals(StepArgs a) {
 // Mean curvature kappa_m = -div(n^)/2 and gas density rho_G = 3 (p_V + 2 sigma kappa_m).
 __global__ __launch_bounds__(256) void k_curvature(StepArgs a) {
     const long long BN = a.g.BN;
-    FOR_LIST(k, a.cnt[C_IF0 + a.parity]) {
-        const long long gid = a.list_old[k];
+    START_COUNTS;
+    for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n0 + n1 + n2;
+         k += (long long)gridDim.x * blockDim.x) {
+        long long gid;
+        if (!start_interface(a, prev, k, n0, n1, gid)) continue;
         const Cell c = decode(a.g, gid);
         double d0, d1, d2, t;
         py_gradient(a.g, c, [&](long long q) { return a.normal[q]; }, d0, t, t);
@@ -237,7 +264,7 @@ __global__ __launch_bounds__(256) void k_curvature(StepArgs a) {
 // (fo buffer); anti-bounce-back for populations arriving from gas, with the
 // cell's velocity of the last step; phi = m/rho; conversion marks.
 template <int ST, int PAR>
-__device__ __forceinline__ void interface_part(const StepArgs &a, const long long gid, const uint8_t fl,
+__device__ __forceinline__ bool interface_part(const StepArgs &a, const long long gid, const uint8_t fl,
                                                const Cell &c, const int (&src)[Q],
                                                typename Codec<ST>::T (&d)[Q]) {
     using C = Codec<ST>;
@@ -306,6 +333,7 @@ __device__ __forceinline__ void interface_part(const StepArgs &a, const long lon
     a.phi_next[gid] = ph;
     const uint8_t mark = ph > 1.0 + a.eps_phi ? F_MARK_A : (ph < -a.eps_phi ? F_MARK_B : 0);
     if (mark) a.flags[gid] = uint8_t(fl | mark);
+    return mark != 0;
 }
 
 // Fused stream + boundary conditions + collision of one liquid (IF = false) or
@@ -314,7 +342,7 @@ __device__ __forceinline__ void interface_part(const StepArgs &a, const long lon
 // (local slots only).  Every cell reads and writes only its own slot set, so
 // cells may be updated in any order and by different kernels.
 template <int ST, int COLL, int PAR, bool IF>
-__device__ __forceinline__ void update_cell(const StepArgs &a, const long long gid, const uint8_t fl) {
+__device__ __forceinline__ bool update_cell(const StepArgs &a, const long long gid, const uint8_t fl) {
     using C = Codec<ST>;
     using T = typename C::T;
     using Mem = typename C::M;
@@ -356,7 +384,8 @@ __device__ __forceinline__ void update_cell(const StepArgs &a, const long long g
         }
     }
 
-    if (IF) interface_part<ST, PAR>(a, gid, fl, c, src, d);
+    bool marked = false;
+    if (IF) marked = interface_part<ST, PAR>(a, gid, fl, c, src, d);
 
     const double *gr = a.grav + 3 * c.b;
     const T om = T(a.omega[c.b]);
@@ -384,53 +413,97 @@ __device__ __forceinline__ void update_cell(const StepArgs &a, const long long g
 #pragma unroll
         for (int i = 1; i < Q; ++i) C::store(fob + (long long)(i - 1) * g.BN + gid, d[i]);
     }
+    return marked;
 }
 
-// Bulk kernel over the liquid cells: one thread per cell, one workgroup per
-// 256 consecutive cells (x fastest, so every PDF access of a wavefront is a
-// contiguous row segment).  Gas and interface cells cost one flag-byte read;
-// interface cells are updated by k_interface, which runs concurrently.
+// Bulk kernel: one thread per cell, 256 consecutive cells per tile (x fastest,
+// so every PDF access of a wavefront is a contiguous row segment).  Only tiles
+// that ever held fluid are listed; the workgroups stride over that list, so a
+// mostly empty domain does not pay for its gas.  Liquid cells get the full
+// stream-collide update.  Interface cells are listed for k_interface in tile
+// order, so the list kernels of the step read neighbouring cells from
+// neighbouring lanes.
 template <int ST, int COLL, int PAR>
 __global__ __launch_bounds__(256) void k_stream_collide(StepArgs a) {
-    const long long gid = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (gid == 0) {
-        // this step's conversion lists start empty (the last step's lengths
-        // stayed readable until now)
-        a.cnt[C_NEWG] = 0;
-        a.cnt[C_FROML] = 0;
-        a.cnt[C_CONV0 + a.parity] = 0;
+    const int p = a.parity;
+    if (blockIdx.x == 0) {
+        // this step's lists start empty (the last step's lengths stayed
+        // readable until now); the next step's interface list too
+        if (threadIdx.x == 0) {
+            a.cnt[C_NEWG] = 0;
+            a.cnt[C_FROML] = 0;
+            a.cnt[C_CONV0 + p] = 0;
+            a.cnt[C_RECV] = 0;
+        }
+        slist_reset(a.list_mark);
+        slist_reset(a.list_if_prev);
     }
-    if (gid >= a.g.BN) return;
-    const uint8_t fl = a.flags[gid];
-    if (fl & F_LIQ) update_cell<ST, COLL, PAR, false>(a, gid, fl);
+    const int32_t ntiles = int32_t((a.g.BN + 255) / 256);
+    const int32_t nt = min(a.cnt[C_TILES], ntiles);
+    for (int32_t k = blockIdx.x; k < nt; k += gridDim.x) {
+        const long long gid = (long long)a.tiles[k] * 256 + threadIdx.x;
+        const bool valid = gid < a.g.BN;
+        const uint8_t fl = valid ? a.flags[gid] : uint8_t(0);
+        const bool is_if = (fl & F_IF) != 0;
+        if (fl & F_LIQ) update_cell<ST, COLL, PAR, false>(a, gid, fl);
+        slist_append(a.list_if, is_if, int32_t(gid), a.cnt + C_ERR);
+    }
+}
+
+// Add v (per lane) to the sharded interface count of the lane's domain; one
+// atomic per wavefront when its lanes share a domain.  All lanes call.
+__device__ __forceinline__ void count_interface(const StepArgs &a, int v, long long gid) {
+    const int b = v ? int(a.g.dN.div(uint32_t(gid))) : -1;
+    const unsigned long long mask = __ballot(v != 0);
+    if (!mask) return;
+    const int lead = __ffsll((long long)mask) - 1;
+    const int b0 = __shfl(b, lead);
+    const int shard = int(((blockIdx.x * blockDim.x + threadIdx.x) >> 6) % unsigned(ND_SHARDS));
+    if (__ballot(v != 0 && b != b0) == 0) {
+        int sum = v;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+        if (__lane_id() == lead) atomicAdd(nif_slot(a.nif_dom, a.parity, a.B, b0, shard), sum);
+    } else if (v) {
+        atomicAdd(nif_slot(a.nif_dom, a.parity, a.B, b, shard), v);
+    }
 }
 
 // Interface cells of the list: the same update plus mass exchange,
-// anti-bounce-back, fill level and conversion marks.  Latency-bound and small,
-// it runs on a second stream beside the bandwidth-bound bulk kernel.
+// anti-bounce-back, fill level and conversion marks; marked cells are listed.
 template <int ST, int COLL, int PAR>
 __global__ __launch_bounds__(256) void k_interface(StepArgs a) {
-    FOR_LIST(k, a.cnt[C_IF0 + a.parity]) {
-        const long long gid = a.list_old[k];
-        update_cell<ST, COLL, PAR, true>(a, gid, a.flags[gid]);
+    __shared__ int32_t pref[257];
+    const SView lst = slist_view(a.list_if, pref);
+    FOR_UNIFORM(k, in, lst.total) {
+        long long gid = 0;
+        bool marked = false;
+        if (in) {
+            gid = sview_at(lst, k);
+            marked = update_cell<ST, COLL, PAR, true>(a, gid, a.flags[gid]);
+        }
+        slist_append(a.list_mark, marked, int32_t(gid), a.cnt + C_ERR);
+        count_interface(a, in ? 1 : 0, gid);
     }
 }
 
 // ------------------------------------------------------------------ conversion
 
-// Conflict rules over the interface list: gas next to a cell filling over
+// Conflict rules over the marked interface cells: gas next to a cell filling over
 // 1+eps becomes a new interface cell; a cell emptying under -eps next to a
 // filling cell stays interface; liquid next to a remaining emptying cell
 // becomes interface.  Each rule reads only the fill marks, so one pass does all.
 // A second loop clears the marks of the cells converted in the last step.
 __global__ __launch_bounds__(256) void k_resolve(StepArgs a) {
     const long long N = a.g.N;
-    FOR_UNIFORM(k, in, clamp_cap(a, a.cnt[C_IF0 + a.parity])) {
+    __shared__ int32_t pref[257];
+    const SView marks = slist_view(a.list_mark, pref);
+    FOR_UNIFORM(k, in, marks.total) {
         uint32_t sel_g = 0, sel_l = 0;
         long long cbase = 0;
         int nb[Q];
         if (in) {
-            const long long gid = a.list_old[k];
+            const long long gid = sview_at(marks, k);
             const Cell c = decode(a.g, gid);
             cbase = (long long)c.b * N;
             neighbours(a.g, c, nb);
@@ -619,22 +692,27 @@ __device__ __forceinline__ double rho_after(const StepArgs &a, const Cell &c, do
 }
 
 // Conversions (Sec. 2.2, 3.1).  Work items: first every new interface cell
-// (refilled by a group of 32 lanes), then every interface cell of the list
-// (filled cells become liquid, emptied cells gas; their excess mass is split
-// over the receivers, or sent to the reservoir), then every from-liquid cell
-// (mass = its density).  The next interface list is built on the way.  The
+// (refilled by a group of 32 lanes), then every marked interface cell (filled
+// cells become liquid, emptied cells gas; their excess mass is split over the
+// receivers, which are claimed and listed, or sent to the reservoir; cells
+// whose emptying was cancelled stay), then every from-liquid cell (mass = its
+// density).  The per-domain interface counts are corrected on the way.  The
 // new cells keep their gas-typed flag until k_excess, so the refill sources
 // read the same validity throughout.
 template <int ST, int SCHEME>
 __global__ __launch_bounds__(256) void k_convert(StepArgs a) {
     const int p = a.parity;
     const long long N = a.g.N;
-    const long long nng = clamp_cap(a, a.cnt[C_NEWG]), nold = clamp_cap(a, a.cnt[C_IF0 + p]),
-                    nfl = clamp_cap(a, a.cnt[C_FROML]);
+    __shared__ int32_t pref[257];
+    const SView marks = slist_view(a.list_mark, pref);
+    const long long nng = clamp_cap(a, a.cnt[C_NEWG]), nmk = marks.total, nfl = clamp_cap(a, a.cnt[C_FROML]);
     const long long R = (nng * 32 + 63) / 64 * 64;   // refill lanes, whole wavefronts
-    FOR_UNIFORM(t, in, R + nold + nfl) {
-        bool is_if = false, conv = false;
-        long long gid = 0;
+    FOR_UNIFORM(t, in, R + nmk + nfl) {
+        bool conv = false;
+        int dn = 0;            // change of the domain's interface count
+        long long gid = 0, cbase = 0;
+        uint32_t sel = 0;      // receivers claimed by this lane
+        int nb[Q];
         if (t < R) {
             // refill: a wavefront never mixes with the items below
             const long long cell = t >> 5;
@@ -642,17 +720,21 @@ __global__ __launch_bounds__(256) void k_convert(StepArgs a) {
             const long long g0 = active ? a.list_newg[cell] : 0;
             refill_group<ST, SCHEME>(a, g0, int(t & 31), active);
             gid = g0;
-            is_if = active && (t & 31) == 0;
+            if (active && (t & 31) == 0) {
+                // a new interface cell may sit in a tile that never held fluid
+                activate_tile(a.tiles, a.tile_bits, a.cnt + C_TILES, int32_t(g0 >> 8),
+                              int32_t((a.g.BN + 255) / 256));
+                dn = 1;
+            }
         } else if (in) {
             const long long k = t - R;
-            gid = k < nold ? a.list_old[k] : a.list_froml[k - nold];
+            gid = k < nmk ? sview_at(marks, k) : a.list_froml[k - nmk];
             const Cell c = decode(a.g, gid);
-            const long long cbase = (long long)c.b * N;
-            if (k < nold) {
+            cbase = (long long)c.b * N;
+            if (k < nmk) {
                 const uint8_t fl = a.flags[gid];
                 if (fl & (F_MARK_A | F_MARK_B)) {
                     const bool fill = (fl & F_MARK_A) != 0;
-                    int nb[Q];
                     neighbours(a.g, c, nb);
                     uint8_t fq[Q];
 #pragma unroll
@@ -660,19 +742,30 @@ __global__ __launch_bounds__(256) void k_convert(StepArgs a) {
                     double d[Q];
                     const double mx = fill ? a.m[gid] - rho_after<ST>(a, c, d) : a.m[gid];
                     int nr = 0;
+                    uint32_t recv = 0;
 #pragma unroll
-                    for (int i = 1; i < Q; ++i) nr += (nb[i] >= 0 && type_after(fq[i]) == F_IF) ? 1 : 0;
+                    for (int i = 1; i < Q; ++i)
+                        if (nb[i] >= 0 && type_after(fq[i]) == F_IF) { ++nr; recv |= 1u << i; }
                     if (nr == 0) {
                         atomicAdd(a.res + p * a.B + c.b, mx);
                         a.mex[gid] = 0.0;
                     } else {
                         a.mex[gid] = mx / nr;
+                        // claim the receivers (each is listed once)
+#pragma unroll
+                        for (int i = 1; i < Q; ++i) {
+                            if (!((recv >> i) & 1u)) continue;
+                            const long long q = cbase + nb[i];
+                            uintptr_t ad = reinterpret_cast<uintptr_t>(a.claim + q);
+                            unsigned int *w = reinterpret_cast<unsigned int *>(ad & ~uintptr_t(3));
+                            const unsigned int bit = 1u << (int(ad & 3) * 8);
+                            if (!(atomicOr(w, bit) & bit)) sel |= 1u << i;
+                        }
                     }
                     a.flags[gid] = uint8_t((fill ? F_LIQ : F_GAS) | F_CONV);
                     a.m[gid] = 0.0;
                     conv = true;
-                } else {
-                    is_if = true;
+                    dn = -1;
                 }
             } else {
                 // from liquid: mass = density; keep a copy of its populations
@@ -681,91 +774,109 @@ __global__ __launch_bounds__(256) void k_convert(StepArgs a) {
 #pragma unroll
                 for (int i = 1; i < Q; ++i) store_fo<ST>(a, i, gid, d[i]);
                 a.flags[gid] = F_IF;
-                is_if = true;
+                dn = 1;
             }
         }
         wave_append(conv, int32_t(gid), a.list_conv, a.cnt + C_CONV0 + p, a.cap, a.cnt + C_ERR);
-        wave_append(is_if, int32_t(gid), a.list_new, a.cnt + C_IF0 + (1 - p), a.cap, a.cnt + C_ERR);
-        // interface cells per domain (one atomic per wave when it is one domain)
-        const int b = is_if ? int(a.g.dN.div(uint32_t(gid))) : -1;
-        const unsigned long long mask = __ballot(is_if);
-        if (mask) {
-            const int lead = __ffsll((long long)mask) - 1;
-            const int b0 = __shfl(b, lead);
-            const bool same = __ballot(is_if && b != b0) == 0;
-            if (same) {
-                if (__lane_id() == lead) atomicAdd(a.nif_dom + p * a.B + b0, __popcll(mask));
-            } else if (is_if) {
-                atomicAdd(a.nif_dom + p * a.B + b, 1);
-            }
-        }
+        wave_append_sel<Q>(sel, [&](int i) { return int32_t(cbase + nb[i]); }, a.list_recv,
+                           a.cnt + C_RECV, a.cap, a.cnt + C_ERR);
+        count_interface(a, dn, gid);
     }
 }
 
-// Every interface cell of the next list gathers the shares of its converted
-// neighbours and the reservoir share, refreshes phi = m/rho if its mass
-// changed, and gets its type and forced filling/emptying class for the next
-// step.  Converted cells get phi in {0, 1} in both fill-level buffers.  Block 0
-// resets the list counters the next step appends to first and carries the
-// reservoir over.
+// Excess mass of one receiver (Sec. 2.2): the shares of its converted
+// neighbours plus the reservoir share r; phi = m/rho* if its mass changed.
+template <int ST>
+__device__ __forceinline__ void receive(const StepArgs &a, long long gid, double r) {
+    const Cell c = decode(a.g, gid);
+    const long long cbase = (long long)c.b * a.g.N;
+    int nb[Q];
+    neighbours(a.g, c, nb);
+    uint8_t fq[Q];
+#pragma unroll
+    for (int i = 1; i < Q; ++i) fq[i] = nb[i] >= 0 ? a.flags[cbase + nb[i]] : uint8_t(0);
+    double add = 0.0;
+    bool touched = false;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        if (fq[i] & F_CONV) {
+            // a converted neighbour that had receivers (it has at least this one)
+            add += a.mex[cbase + nb[i]];
+            touched = true;
+        }
+    }
+    double m = a.m[gid];
+    if (touched) m = m + add;
+    if (r != 0.0) {
+        m = m + r;
+        touched = true;
+    }
+    if (touched) {
+        double d[Q];
+        a.m[gid] = m;
+        a.phi_next[gid] = m / rho_after<ST>(a, c, d);
+    }
+}
+
+// Excess-mass redistribution and the end of the step.  Receivers gather the
+// shares of their converted neighbours.  Every interface cell after the
+// conversions (this step's list entries that are still interface, the new and
+// the from-liquid cells) gets its type and forced class, and in a domain whose
+// reservoir is spread its share of it (receivers of such a domain are left to
+// this loop).  Converted cells get phi in {0, 1} in both fill-level buffers.
+// Block 0 carries the reservoir over and resets the counters the next step
+// needs at zero.
 template <int ST>
 __global__ __launch_bounds__(256) void k_excess(StepArgs a) {
     const int p = a.parity;
-    const long long N = a.g.N;
+    const double *res = a.res + p * a.B;
+    // the reservoir is spread when it holds mass and the domain has interface cells
+    auto spreads = [&](int b) { return res[b] != 0.0 && nif_sum(a.nif_dom, p, a.B, b) > 0; };
     if (blockIdx.x == 0) {
         for (int b = threadIdx.x; b < a.B; b += blockDim.x) {
             // mass that found no receiver is kept while the domain has no interface
-            a.res[(1 - p) * a.B + b] = a.nif_dom[p * a.B + b] > 0 ? 0.0 : a.res[p * a.B + b];
-            a.nif_dom[(1 - p) * a.B + b] = 0;
+            a.res[(1 - p) * a.B + b] = spreads(b) ? 0.0 : res[b];
         }
-        if (threadIdx.x == 0) {
-            a.cnt[C_IF0 + p] = 0;   // this step's list is dead; the next step appends to it
-            a.cnt[C_BAND] = 0;
-        }
+        for (int k = threadIdx.x; k < a.B * ND_SHARDS; k += blockDim.x)
+            *nif_slot(a.nif_dom, 1 - p, a.B, k / ND_SHARDS, k % ND_SHARDS) = 0;
+        if (a.rhoG) slist_reset(a.list_band);   // the band list exists with surface tension only
     }
-    const double *res = a.res + p * a.B;
-    const int32_t *nif = a.nif_dom + p * a.B;
-    FOR_LIST(k, a.cnt[C_IF0 + (1 - p)]) {
-        const long long gid = a.list_new[k];
+    bool spread_any = false;
+    for (int b = threadIdx.x; b < a.B; b += blockDim.x) spread_any |= spreads(b);
+    spread_any = __syncthreads_or(spread_any);
+    FOR_LIST(k, a.cnt[C_RECV]) {
+        const long long gid = a.list_recv[k];
+        a.claim[gid] = 0;
+        if (!spread_any || !spreads(int(a.g.dN.div(uint32_t(gid))))) receive<ST>(a, gid, 0.0);
+    }
+    // every interface cell after the conversions: its forced filling/emptying
+    // class (Thuerey) from the final neighbour types, and in a domain whose
+    // reservoir is spread its share
+    __shared__ int32_t pref[257];
+    const SView lst = slist_view(a.list_if, pref);
+    const long long n0 = lst.total, n1 = clamp_cap(a, a.cnt[C_NEWG]), n2 = clamp_cap(a, a.cnt[C_FROML]);
+    for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n0 + n1 + n2;
+         k += (long long)gridDim.x * blockDim.x) {
+        long long gid;
+        if (k < n0) {
+            gid = sview_at(lst, k);
+            if (type_after(a.flags[gid]) != F_IF) continue;
+        } else {
+            gid = k - n0 < n1 ? a.list_newg[k - n0] : a.list_froml[k - n0 - n1];
+        }
         const Cell c = decode(a.g, gid);
-        const long long cbase = (long long)c.b * N;
+        const long long cbase = (long long)c.b * a.g.N;
         int nb[Q];
         neighbours(a.g, c, nb);
-        uint8_t fq[Q];
-        double mx[Q];
+        bool has_liq = false, has_gas = false;
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
-            const long long q = cbase + (nb[i] >= 0 ? nb[i] : c.n);
-            fq[i] = nb[i] >= 0 ? a.flags[q] : uint8_t(0);
-            mx[i] = a.mex[q];
-        }
-        double add = 0.0;
-        bool touched = false, has_liq = false, has_gas = false;
-#pragma unroll
-        for (int i = 1; i < Q; ++i) {
-            if (fq[i] & F_CONV) {
-                // a converted neighbour that had receivers (it has at least this one)
-                add += mx[i];
-                touched = true;
-            }
-            const uint8_t ty = type_after(fq[i]);
+            const uint8_t ty = nb[i] >= 0 ? type_after(a.flags[cbase + nb[i]]) : uint8_t(0);
             has_liq |= ty == F_LIQ;
             has_gas |= ty == F_GAS;
         }
-        const double r = res[c.b];
-        const int nd = nif[c.b];
-        double m = a.m[gid];
-        if (touched) m = m + add;
-        if (r != 0.0 && nd > 0) {
-            m = m + r / nd;
-            touched = true;
-        }
-        if (touched) {
-            double d[Q];
-            a.m[gid] = m;
-            a.phi_next[gid] = m / rho_after<ST>(a, c, d);
-        }
         a.flags[gid] = uint8_t(F_IF | (!has_liq ? F_NOFLUID : (!has_gas ? F_NOEMPTY : 0)));
+        if (spread_any && spreads(c.b)) receive<ST>(a, gid, res[c.b] / nif_sum(a.nif_dom, p, a.B, c.b));
     }
     FOR_LIST(k, a.cnt[C_CONV0 + p]) {
         const long long gid = a.list_conv[k];
@@ -786,34 +897,18 @@ static int list_blocks(long long cap) {
 
 template <typename K>
 static void launch_bulk(K kernel, const StepArgs &a, hipStream_t s) {
-    const unsigned blocks = unsigned((a.g.BN + 255) / 256);
-    hipLaunchKernelGGL(kernel, dim3(blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(kernel, dim3(unsigned(a.bulk_grid)), dim3(256), 0, s, a);
 }
 
 template <int ST>
 static void launch_step_t(const StepArgs &a, int collision, int scheme, hipStream_t s,
-                          const BulkEvents *ev, const SideStream &side) {
+                          const BulkEvents *ev) {
     const int lb = list_blocks(a.cap);
     if (a.rhoG) {
         hipLaunchKernelGGL(k_band, dim3(lb), dim3(256), 0, s, a);
         hipLaunchKernelGGL(k_normals, dim3(lb), dim3(256), 0, s, a);
         hipLaunchKernelGGL(k_curvature, dim3(lb), dim3(256), 0, s, a);
     }
-    // fork: interface cells on the side stream, liquid cells on the main one.
-    // The interface kernel gets a small grid: it only has to finish within the
-    // bulk kernel's time, and every resident interface wavefront holds half a
-    // SIMD's registers that the bulk kernel would otherwise use.
-    const int ib = lb < 256 ? lb : 256;
-    (void)hipEventRecord(side.fork, s);
-    (void)hipStreamWaitEvent(side.stream, side.fork, 0);
-    if (collision == 0) {
-        if (a.parity == 0) hipLaunchKernelGGL((k_interface<ST, 0, 0>), dim3(ib), dim3(256), 0, side.stream, a);
-        else hipLaunchKernelGGL((k_interface<ST, 0, 1>), dim3(ib), dim3(256), 0, side.stream, a);
-    } else {
-        if (a.parity == 0) hipLaunchKernelGGL((k_interface<ST, 1, 0>), dim3(ib), dim3(256), 0, side.stream, a);
-        else hipLaunchKernelGGL((k_interface<ST, 1, 1>), dim3(ib), dim3(256), 0, side.stream, a);
-    }
-    (void)hipEventRecord(side.join, side.stream);
     if (ev) (void)hipEventRecord(ev->before, s);
     if (collision == 0) {
         if (a.parity == 0) launch_bulk(k_stream_collide<ST, 0, 0>, a, s);
@@ -823,7 +918,13 @@ static void launch_step_t(const StepArgs &a, int collision, int scheme, hipStrea
         else launch_bulk(k_stream_collide<ST, 1, 1>, a, s);
     }
     if (ev) (void)hipEventRecord(ev->after, s);
-    (void)hipStreamWaitEvent(s, side.join, 0);   // join
+    if (collision == 0) {
+        if (a.parity == 0) hipLaunchKernelGGL((k_interface<ST, 0, 0>), dim3(lb), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_interface<ST, 0, 1>), dim3(lb), dim3(256), 0, s, a);
+    } else {
+        if (a.parity == 0) hipLaunchKernelGGL((k_interface<ST, 1, 0>), dim3(lb), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_interface<ST, 1, 1>), dim3(lb), dim3(256), 0, s, a);
+    }
     hipLaunchKernelGGL(k_resolve, dim3(lb), dim3(256), 0, s, a);
     switch (scheme) {
         case 0: hipLaunchKernelGGL((k_convert<ST, 0>), dim3(lb), dim3(256), 0, s, a); break;
@@ -840,20 +941,19 @@ static void launch_step_t(const StepArgs &a, int collision, int scheme, hipStrea
 #if defined(FSLBM_UNIT_STORAGE)
 template <>
 void launch_step_storage<FSLBM_UNIT_STORAGE>(const StepArgs &a, int collision, int scheme,
-                                             hipStream_t s, const BulkEvents *ev,
-                                             const SideStream &side) {
-    launch_step_t<FSLBM_UNIT_STORAGE>(a, collision, scheme, s, ev, side);
+                                             hipStream_t s, const BulkEvents *ev) {
+    launch_step_t<FSLBM_UNIT_STORAGE>(a, collision, scheme, s, ev);
 }
 #endif
 
 #if defined(FSLBM_UNIT_DISPATCH)
 void launch_step(const StepArgs &a, int storage, int collision, int scheme, hipStream_t s,
-                 const SideStream &side, const BulkEvents *ev) {
+                 const BulkEvents *ev) {
     switch (storage) {
-        case ST_F64: launch_step_storage<ST_F64>(a, collision, scheme, s, ev, side); break;
-        case ST_F32: launch_step_storage<ST_F32>(a, collision, scheme, s, ev, side); break;
-        case ST_F16: launch_step_storage<ST_F16>(a, collision, scheme, s, ev, side); break;
-        default: launch_step_storage<ST_BF16>(a, collision, scheme, s, ev, side); break;
+        case ST_F64: launch_step_storage<ST_F64>(a, collision, scheme, s, ev); break;
+        case ST_F32: launch_step_storage<ST_F32>(a, collision, scheme, s, ev); break;
+        case ST_F16: launch_step_storage<ST_F16>(a, collision, scheme, s, ev); break;
+        default: launch_step_storage<ST_BF16>(a, collision, scheme, s, ev); break;
     }
 }
 #endif

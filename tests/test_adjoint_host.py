@@ -72,12 +72,17 @@ def test_stored_differences_are_reproducible_and_converged():
         vals[k] = R.run_loss(pk, sk, e["target"], case["T"], gold["x_probe"])[0]
     c4 = (8.0 * (vals[1] - vals[-1]) - (vals[2] - vals[-2])) / (12.0 * d)
     assert c4 == ref["ref"]
-    # the references the GPU tests hold to 1e-6 are converged well below that
+    # the d/da0 and d/dg references are converged below half of the 1e-6 bar,
+    # so the GPU test's widening to twice the spread never applies to them;
+    # d/domega is physically tiny in the short windows (1e-10 .. 1e-8) and is
+    # held there to its own spread, but converged to 1e-6 over 300 steps
     for c in gold["cases"]:
         for ent in c["entries"]:
             for name in ("a0", "g", "omega"):
                 r = ent["grads"][name]
                 assert r is not None, (c["name"], ent["seed"], name)
-                if name == "omega" and c["T"] <= 60:
-                    continue   # d/d omega is ~1e-10 in 60 steps: held to its own spread
-                assert abs(r["ref"] - r["confirm"]) <= 1e-7 * abs(r["ref"]), (c["name"], ent["seed"], name, r)
+                spread = abs(r["ref"] - r["confirm"]) / abs(r["ref"])
+                if name != "omega":
+                    assert spread <= 5e-7, (c["name"], ent["seed"], name, r)
+                elif c["T"] >= 300:
+                    assert spread <= 1e-6, (c["name"], ent["seed"], name, r)

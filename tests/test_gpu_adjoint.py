@@ -1,0 +1,212 @@
+"""Reverse mode on the GPU against the oracle's central finite differences.
+
+The reference values in ``golden/adjoint_fd.json`` are written by
+``golden/make_adjoint_fd.py`` from the FP64 oracle alone.  Each test runs the
+library's checkpointed forward and hand-written adjoint through the C ABI (via
+``paper_2207_14496_amd.adjoint.height_loss``, a torch.autograd.Function) and
+compares, per domain:
+  * the loss (and the height trajectory where stored) with the oracle's;
+  * dL/d omega, dL/d g and dL/d a0 (a0 through the torch-written fill-level
+    initializer) with the reference differences;
+  * dL/d phi0, dL/d m0 and dL/d f0 of sampled start-state entries.
+Bar: relative error <= 1e-6, widened only where the reference's own
+uncertainty (the spread between its two ladder steps) is larger, with an
+absolute floor of 1e-14 for entries the loss does not depend on.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from _gpu import announce
+from paper_2207_14496_amd import adjoint, fslbm
+
+pytestmark = pytest.mark.gpu
+
+GOLD_PATH = os.path.join(os.path.dirname(__file__), "golden", "adjoint_fd.json")
+with open(GOLD_PATH) as fh:
+    GOLD = json.load(fh)
+CASES = {c["name"]: c for c in GOLD["cases"]}
+X_PROBE = GOLD["x_probe"]
+REL = 1e-6
+
+
+def window(case, K=0):
+    g = case["geometry"]
+    return adjoint.Window(g["nx"], g["ny"], 1, (1, 0, 1), case["T"], X_PROBE, K)
+
+
+def run(case, entries, K=0, targets=None, dloss=None):
+    """Forward + backward for a batch of golden entries.  Returns (loss [B],
+    height [B, T+1], grads dict of numpy arrays)."""
+    g = case["geometry"]
+    dev = "cuda"
+    a0 = torch.tensor([e["params"]["a0"] for e in entries], dtype=torch.float64, device=dev,
+                      requires_grad=True)
+    om = torch.tensor([e["params"]["omega"] for e in entries], dtype=torch.float64, device=dev,
+                      requires_grad=True)
+    gv = torch.tensor([[0.0, -e["params"]["g"], 0.0] for e in entries], dtype=torch.float64,
+                      device=dev, requires_grad=True)
+    flags, pdf0, mass0, phi0 = adjoint.standing_wave_state(a0, g["nx"], g["ny"], g["depth"], dev)
+    pdf0.requires_grad_(True)
+    # m0 = phi0 on interface cells, so phi0's own gradient also collects dL/dm0;
+    # the loss gets a copy of phi0 whose gradient is the start-state phi part alone
+    phi_in = phi0.clone()
+    mass0.retain_grad()
+    phi_in.retain_grad()
+    if targets is None:
+        targets = [e["target"] for e in entries]
+    tgt = torch.tensor(np.asarray(targets), dtype=torch.float64, device=dev)
+    loss = adjoint.height_loss(om, gv, pdf0, mass0, phi_in, flags, tgt, window(case, K))
+    height = loss.grad_fn.height
+    w = torch.ones_like(loss) if dloss is None else torch.as_tensor(dloss, dtype=torch.float64,
+                                                                    device=dev)
+    (loss * w).sum().backward()
+    grads = dict(a0=a0.grad.cpu().numpy(), omega=om.grad.cpu().numpy(),
+                 g=-gv.grad[:, 1].cpu().numpy(), gvec=gv.grad.cpu().numpy(),
+                 phi=phi_in.grad.cpu().numpy(), mass=mass0.grad.cpu().numpy(),
+                 pdf=pdf0.grad.cpu().numpy())
+    return loss.detach().cpu().numpy(), height, grads
+
+
+ATOL = 1e-14   # below the resolution of any difference here (exact zeros: no dependence)
+
+
+def check(got, ref, what, report):
+    """|got - ref| <= max(1e-6 |ref|, 2 |ref - confirm|, 1e-14)."""
+    r, c = ref["ref"], ref["confirm"]
+    tol = max(REL * abs(r), 2.0 * abs(r - c), ATOL)
+    err = abs(got - r)
+    report.append(f"{what}: adjoint {got:+.12e} fd {r:+.12e} rel {err / max(abs(r), 1e-300):.2e}")
+    assert err <= tol, "\n".join(report)
+
+
+def check_case(case, entries, loss, height, grads, cells=True):
+    report = []
+    for b, e in enumerate(entries):
+        lref = e["loss"]
+        assert abs(loss[b] - lref) <= 1e-8 * lref + 1e-15, f"loss {loss[b]} vs oracle {lref}"
+        if "height" in e and height is not None:
+            dh = np.max(np.abs(np.asarray(height[b]) - np.asarray(e["height"])))
+            assert dh <= 1e-9, f"seed {e['seed']}: height differs from the oracle by {dh:.3e}"
+        for name in ("omega", "g", "a0"):
+            ref = e["grads"][name]
+            assert ref is not None, f"no finite-difference reference for {name}"
+            check(grads[name][b], ref, f"{case['name']} seed {e['seed']} d/d{name}", report)
+        if cells and "cells" in e:
+            for cell in e["cells"]:
+                if cell["fd"] is None:
+                    continue
+                idx = cell["index"]
+                if cell["field"] == "f":
+                    got = grads["pdf"][b, idx[0], idx[1]]
+                else:
+                    got = grads[{"phi": "phi", "m": "mass"}[cell["field"]]][b, idx]
+                check(got, cell["fd"], f"{case['name']} seed {e['seed']} d/d{cell['field']}{idx}", report)
+    print("\n".join(report))
+
+
+@pytest.mark.parametrize("name", ["wave64_T60", "wave128_T60", "wave64_T300", "wave128_T200"])
+def test_adjoint_matches_oracle_differences(name):
+    case = CASES[name]
+    entries = case["entries"]
+    announce(f"adjoint {name}: batch of {len(entries)}, T={case['T']}")
+    loss, height, grads = run(case, entries)
+    check_case(case, entries, loss, height, grads)
+
+
+def test_adjoint_full_configuration_batch_of_64():
+    """The differentiable configuration at full size: 128 x 256 standing wave,
+    4000 steps, 64 seeded domains in one launch with sqrt(T) checkpoints.  Over
+    4000 steps each domain converts about 3100 cells, so no finite difference
+    keeps the cell-type sequence; this checks the properties that hold at any
+    size instead: finite gradients, and every domain's loss and gradient equal
+    to the ones of the same domain run in a batch of two."""
+    from paper_2207_14496_amd import setups
+    g = dict(nx=128, ny=256, depth=128.0, a0=1.28, omega=1.8, g=1e-5)
+    T, B = 4000, 64
+    case = dict(name="wave128_T4000", geometry=g, T=T)
+    pert = []
+    for s in range(B):
+        x1, x2, x3 = setups.target_perturbation(s)
+        pert.append(dict(a0=g["a0"] * (1 + x3), omega=g["omega"] * (1 + x1), g=g["g"] * (1 + x2)))
+    announce("adjoint 128x256 T=4000: target runs for 64 domains")
+    a0 = torch.tensor([p["a0"] for p in pert], dtype=torch.float64, device="cuda")
+    flags, pdf0, mass0, phi0 = adjoint.standing_wave_state(a0, g["nx"], g["ny"], g["depth"])
+    params = fslbm.Params(g["nx"], g["ny"], 1, B, (1, 0, 1), fslbm.SRT, fslbm.F64, fslbm.REFILL_EQ,
+                          g["omega"], omega_b=[p["omega"] for p in pert],
+                          gravity_b=[(0.0, -p["g"], 0.0) for p in pert])
+    sim = fslbm.Simulation(params, flags, phi0, pdf=pdf0, mass=mass0)
+    h = np.zeros((B, T + 1))
+    for t in range(1, T + 1):
+        sim.step(1)
+        phi = sim.read(("phi",))["phi"].view(B, g["ny"], g["nx"])
+        h[:, t] = phi[:, :, X_PROBE].sum(dim=1).cpu().numpy()
+    sim.close()
+    base = dict(a0=g["a0"], omega=g["omega"], g=g["g"])
+    entries = [dict(seed=s, params=base) for s in range(B)]
+    announce("adjoint 128x256 T=4000: forward + backward, batch of 64")
+    loss, _, grads = run(case, entries, targets=h[:, 1:])
+    assert np.all(np.isfinite(loss)) and all(np.all(np.isfinite(v)) for v in grads.values())
+    assert np.all(loss > 0)
+    pick = [0, 37]
+    announce("adjoint 128x256 T=4000: domains 0 and 37 as a batch of two")
+    loss2, _, grads2 = run(case, [entries[k] for k in pick], targets=h[pick, 1:])
+    np.testing.assert_allclose(loss2, loss[pick], rtol=1e-13, atol=0)
+    for name in ("a0", "omega", "g"):
+        np.testing.assert_allclose(grads2[name], grads[name][pick], rtol=1e-11, atol=0)
+    np.testing.assert_allclose(grads2["phi"], grads["phi"][pick], rtol=1e-9, atol=1e-18)
+
+
+def test_checkpoint_count_does_not_change_the_gradient():
+    case = CASES["wave64_T300"]
+    entries = case["entries"]
+    announce("adjoint checkpoint counts 1, 17, 300")
+    res = [run(case, entries, K=k) for k in (1, 17, 300)]
+    for loss, _, grads in res[1:]:
+        np.testing.assert_allclose(loss, res[0][0], rtol=1e-12, atol=0)
+        for name in ("a0", "omega", "g"):
+            np.testing.assert_allclose(grads[name], res[0][2][name], rtol=1e-10, atol=0)
+        np.testing.assert_allclose(grads["phi"], res[0][2]["phi"], rtol=1e-9, atol=1e-18)
+
+
+def test_backward_is_linear_in_the_incoming_adjoint():
+    case = CASES["wave64_T300"]
+    entries = case["entries"]
+    announce("adjoint linearity in dL")
+    _, _, g1 = run(case, entries)
+    w = np.array([2.0, 0.0, -0.5])
+    _, _, g2 = run(case, entries, dloss=w)
+    for name in ("a0", "omega", "g"):
+        np.testing.assert_allclose(g2[name], w * g1[name], rtol=1e-12, atol=1e-300)
+
+
+def test_adjoint_rejects_unsupported_configurations():
+    announce("adjoint configuration checks")
+    nx, ny = 16, 16
+    B = 1
+    flags = np.full((B, nx * ny), fslbm.LIQUID, np.uint8)
+    flags[:, nx * (ny - 2):] = fslbm.GAS
+    flags[:, nx * (ny - 3):nx * (ny - 2)] = fslbm.INTERFACE
+    phi = np.where(flags == fslbm.LIQUID, 1.0, np.where(flags == fslbm.INTERFACE, 0.5, 0.0))
+    rho = np.ones((B, nx * ny))
+    u = np.zeros((B, 3, nx * ny))
+    tgt = np.zeros((B, 4))
+    for kw, msg in ((dict(collision=fslbm.TRT), "SRT"), (dict(storage=fslbm.F32), "F64"),
+                    (dict(sigma=1e-4), "sigma"), (dict(refill=fslbm.REFILL_GEQ), "EQ")):
+        p = fslbm.Params(nx, ny, 1, B, (1, 0, 1), gravity=(0.0, -1e-5, 0.0))
+        for k, v in kw.items():
+            setattr(p, k, v)
+        sim = fslbm.Simulation(p, flags, phi, rho, u)
+        with pytest.raises(fslbm.FslbmError, match=msg):
+            sim.adjoint_forward(tgt, 4, 3)
+        sim.close()
+    p = fslbm.Params(nx, ny, 1, B, (1, 0, 1), gravity=(0.0, -1e-5, 0.0))
+    sim = fslbm.Simulation(p, flags, phi, rho, u)
+    with pytest.raises(fslbm.FslbmError):
+        sim.adjoint_backward()
+    with pytest.raises(fslbm.FslbmError, match="x_probe"):
+        sim.adjoint_forward(tgt, 4, nx)
+    sim.close()
