@@ -8,10 +8,15 @@ storage with FP64 mass / fill level.  Synthetic, seeded geometry (no dataset).
 
 value      MLUPS_fluid = (liquid + interface cells) x steps / time, whole job,
            state resident in HBM, steps replayed as HIP graphs.
-roofline   the bulk stream-collide kernel: algorithmic bytes per launch (one
-           flag byte per cell + 19 PDFs read and written per fluid cell +
-           40 B per interface cell) / its average duration, measured live with
-           HIP events around every bulk launch of a second pass of steps.
+roofline   the bulk stream-collide kernel: algorithmic bytes per launch (per
+           liquid cell 19 PDFs read and written plus its flag byte; per
+           interface cell its flag byte and its 4-byte list entry) / its
+           average duration, measured live with HIP events around every bulk
+           launch of a second pass of steps.  `traffic` is the HBM bytes per
+           launch that rocprofv3 FETCH_SIZE + WRITE_SIZE counted, scaled by
+           the same counters' reading for a device copy of known size
+           (--calibrate-copy), when such a measurement of the current kernel
+           source is on record.
 cpu_baseline  the FP64 CPU oracle (single thread) on a bounded sample of the
            same workload.
 variants   other storage types, the dense pool-wave case (83% fluid), and the
@@ -37,9 +42,11 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def bulk_bytes(n_cells, n_fluid, n_if, storage_bytes):
-    """Algorithmic HBM bytes of one bulk stream-collide launch."""
-    return n_cells * 1 + n_fluid * 38 * storage_bytes + n_if * 40
+def bulk_bytes(n_liquid, n_if, storage_bytes):
+    """Algorithmic HBM bytes of one bulk stream-collide launch: every liquid cell
+    reads and writes its 19 PDFs and reads its flag; every interface cell has its
+    flag read and is written to the interface list."""
+    return n_liquid * (38 * storage_bytes + 1) + n_if * (1 + 4)
 
 
 def kernel_src_hash():
@@ -81,15 +88,16 @@ def run_case(fslbm, setup, storage, steps, warmup, timed_steps, use_graphs=True)
     d1 = sim.diagnostics()[0]
     fluid = 0.5 * ((d0["n_liquid"] + d0["n_interface"]) + (d1["n_liquid"] + d1["n_interface"]))
     n_if = 0.5 * (d0["n_interface"] + d1["n_interface"])
+    n_liq = 0.5 * (d0["n_liquid"] + d1["n_liquid"])
     bulk_ms, total_ms = sim.step_timed(timed_steps)
     d2 = sim.diagnostics()[0]
-    out = dict(sim=sim, ms=ms, fluid=fluid, n_if=n_if, d0=d0, d1=d1, d2=d2,
+    out = dict(sim=sim, ms=ms, fluid=fluid, n_if=n_if, n_liq=n_liq, d0=d0, d1=d1, d2=d2,
                bulk_ms_avg=bulk_ms / timed_steps, timed_total_ms=total_ms)
     return out
 
 
 def roofline(setup, storage_bytes, r, traffic):
-    nbytes = bulk_bytes(setup.N, r["fluid"], r["n_if"], storage_bytes)
+    nbytes = bulk_bytes(r["n_liq"], r["n_if"], storage_bytes)
     achieved = nbytes / (r["bulk_ms_avg"] * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -133,6 +141,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--variant-steps", type=int, default=300)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 1 GiB elementwise copy kernel 5 times (HBM counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -142,6 +152,14 @@ def main():
 
     sys.path.insert(0, ROOT)
     import torch
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            torch.mul(src, 2.0, out=dst)   # one elementwise kernel: reads and writes 1 GiB
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_dispatch": 1 << 30, "dispatches": 5}), flush=True)
+        return
     from paper_2207_14496_amd import fslbm, setups
 
     storage = {"f64": fslbm.F64, "f32": fslbm.F32, "f16": fslbm.F16, "bf16": fslbm.BF16}[args.storage]
