@@ -200,10 +200,32 @@ def main():
 
     if not args.no_variants:
         result["variants"] = variants(fslbm, setups, torch, args)
+        result["wave_frequency"] = wave_frequency(fslbm)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
         result["cpu_baseline"] = cpu_baseline(setup)
     print(json.dumps(result), flush=True)
+
+
+def wave_frequency(fslbm, L=400, t_star_end=10.0):
+    """Sec. 4.1 gravity wave at L = 400 in every storage type: the first two
+    half-periods T*/2 and their error against the FP64 run and against the
+    analytic pi."""
+    import math
+    from paper_2207_14496_amd import waves
+    out, ref = [], None
+    for name, st in (("f64", fslbm.F64), ("f32", fslbm.F32), ("f16", fslbm.F16), ("bf16", fslbm.BF16)):
+        t, a, s, _ = waves.run(L, st, t_star_end=t_star_end, every=20)
+        hp = [float(v) for v in waves.half_periods(t, a)[:2]]
+        rec = {"storage": name, "L": L, "half_periods": [round(v, 5) for v in hp],
+               "rel_err_vs_pi": [round(v / math.pi - 1, 5) for v in hp]}
+        if ref is None:
+            ref = hp
+        else:
+            rec["rel_err_vs_f64"] = [round(v / r - 1, 6) for v, r in zip(hp, ref)]
+        out.append(rec)
+        log(f"  gravity wave L={L} {name}: T*/2 = {rec['half_periods']}")
+    return out
 
 
 def variants(fslbm, setups, torch, args):

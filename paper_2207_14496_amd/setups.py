@@ -195,6 +195,25 @@ def standing_wave(nx=64, ny=128, depth=64.0, amplitude=0.64, omega=1.8, g=1e-5,
     return _finish(s, phi3, rho3)
 
 
+def gravity_wave(L=200, reynolds=10.0, omega=1.8, refill=0, name="gravity-wave") -> Setup:
+    """The gravity wave of Sec. 4.1: L x L x 1, periodic x, walls in y, depth d = L/2,
+    eta(x) = d + a0 cos(k x) with a0 = 0.01 L and k = 2 pi / L, SRT omega, rest
+    fluid with hydrostatic density referred to the mean depth (pressure p0 at
+    y = d); g from Re = a0 omega0 L / nu = 10 with omega0^2 = g k tanh(k d) and
+    nu = (1/omega - 1/2) / 3.  meta holds d, a0, k, nu, omega0 and the period."""
+    d, a0, k = 0.5 * L, 0.01 * L, 2.0 * np.pi / L
+    nu = (1.0 / omega - 0.5) / 3.0
+    omega0 = reynolds * nu / (a0 * L)
+    g = omega0 ** 2 / (k * np.tanh(k * d))
+    s = Setup(name, L, L, 1, (1, 0, 1), 0, omega, (0.0, -g, 0.0), refill=refill)
+    phi3 = height_fill(L, L, 1, lambda x: d + a0 * np.cos(k * x), axis_up=1)
+    yc = _centres(L)[None, :, None]
+    rho3 = np.broadcast_to(1.0 + 3.0 * g * (d - yc), (1, L, L)).copy()
+    s.meta = dict(depth=d, amplitude=a0, wavenumber=k, nu=nu, omega0=omega0,
+                  period=2.0 * np.pi / omega0, g=g)
+    return _finish(s, phi3, rho3)
+
+
 def rect_dam_break(nx=256, ny=128, nz=64, width=64, height=32, omega=1.95, g=2e-5,
                    refill=0, name="rect-dam-break") -> Setup:
     """Rectangular dam break: liquid box x < width, z < height, all y, against the

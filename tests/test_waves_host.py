@@ -1,0 +1,44 @@
+"""The gravity-wave monitor (no GPU) and the values the paper prints for it.
+
+Pins: on an exactly damped cosine the monitor returns T*/2 = pi and the
+decrement it was built with; the paper's printed analytic series (Sec. 4.1)
+equals the closed forms T*/2 = pi and delta = 2 nu k^2 T = 0.016 pi^3 (for
+a0 = 0.01 L and Re = 10) to float32 precision; the setup reproduces g = 6.85e-6
+at L = 200 and the stated Reynolds number."""
+import json
+import os
+
+import numpy as np
+
+from paper_2207_14496_amd import setups, waves
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "gravity_wave_sec41.json")))
+
+
+def test_monitor_on_an_exact_damped_cosine():
+    t = np.linspace(0.0, 40.0, 40001)
+    delta = 0.4961004
+    a = np.exp(-delta / (2 * np.pi) * t) * np.cos(t)
+    hp = waves.half_periods(t, a)
+    assert np.allclose(hp[:6], np.pi, rtol=0, atol=1e-6)
+    ld = waves.log_decrements(t, a)
+    # the damped maxima sit slightly before the cosine's (tan t = -delta / 2 pi)
+    assert abs(ld[0][0] - (2 * np.pi - np.arctan(delta / (2 * np.pi)))) < 1e-3 and all(abs(d - delta) < 1e-7 for _, d in ld[:5])
+
+
+def test_printed_analytic_values_are_the_closed_forms():
+    assert all(abs(v - np.pi) < 1e-6 for v in GOLD["analytic_half_period"])
+    closed = 0.016 * np.pi ** 3            # 2 nu k^2 T with Re = a0 omega0 L / nu = 10, a0 = L/100
+    later = [d for _, d in GOLD["analytic_log_decrement"][1:]]
+    assert all(abs(d - closed) < 1e-6 for d in later)
+
+
+def test_gravity_wave_setup_parameters():
+    s = setups.gravity_wave(200)
+    m = s.meta
+    assert abs(m["g"] - 6.848e-6) < 1e-9
+    assert abs(m["amplitude"] * m["omega0"] * 200 / m["nu"] - 10.0) < 1e-12
+    assert abs(m["omega0"] ** 2 - m["g"] * m["wavenumber"] * np.tanh(m["wavenumber"] * m["depth"])) < 1e-20
+    # rest state: the surface column at x = 0 holds d + a0 cos(k/2) of liquid
+    h0 = s.phi.reshape(200, 200)[:, 0].sum()
+    assert abs(h0 - (m["depth"] + m["amplitude"] * np.cos(0.5 * m["wavenumber"]))) < 1e-3
