@@ -57,7 +57,7 @@ bool make_layout(const fslbm_params &p, Layout &L) {
     L.grav = take(size_t(p.batch) * 24);
     L.diag_d = take(size_t(p.batch) * DIAG_BLOCKS * 2 * 8);
     L.diag_i = take(size_t(p.batch) * DIAG_BLOCKS * 4 * 8);
-    const size_t ntiles = size_t((BN + 255) / 256);
+    const size_t ntiles = size_t(tile_count(BN));
     L.tiles = take(ntiles * 4);
     L.tile_bits = take((ntiles + 31) / 32 * 4);
     L.total = off;
@@ -189,12 +189,31 @@ __global__ void k_init_lists(StepArgs a) {
     slist_append(a.list_if_prev, is_if, int32_t(gid), a.cnt + C_ERR);
 }
 
-// The tiles (256 consecutive cells) that hold liquid or interface cells.
+// The tiles (one wavefront of consecutive cells each) that hold liquid or
+// interface cells.
+// The list and its bits start empty; one list atomic per workgroup.
 __global__ __launch_bounds__(256) void k_init_tiles(StepArgs a) {
+    static_assert(TILE == 64, "one tile per wavefront");
+    __shared__ uint32_t has;
+    __shared__ int32_t base;
     const long long gid = (long long)blockIdx.x * 256 + threadIdx.x;
     const bool fluid = gid < a.g.BN && (a.flags[gid] & (F_LIQ | F_IF));
-    if (__syncthreads_or(fluid) && threadIdx.x == 0)
-        activate_tile(a.tiles, a.tile_bits, a.cnt + C_TILES, int32_t(blockIdx.x), int32_t(gridDim.x));
+    const int w = int(threadIdx.x >> 6);
+    const bool any = __ballot(fluid) != 0;
+    if (threadIdx.x == 0) has = 0;
+    __syncthreads();
+    if (any && __lane_id() == 0) atomicOr(&has, 1u << w);
+    __syncthreads();
+    const int32_t t0 = int32_t(blockIdx.x) * 4;   // the workgroup's four tiles share one bit word
+    if (threadIdx.x == 0 && has) {
+        base = atomicAdd(a.cnt + C_TILES, __popc(has));
+        atomicOr(a.tile_bits + (t0 >> 5), has << (t0 & 31));
+    }
+    __syncthreads();
+    if (any && __lane_id() == 0) {
+        const int32_t pos = base + __popc(has & ((1u << w) - 1u));
+        if (pos < int32_t(tile_count(a.g.BN))) a.tiles[pos] = t0 + w;
+    }
 }
 
 // ------------------------------------------------------------------ read-back
@@ -448,7 +467,7 @@ bool load_state(fslbm_ctx *c, const uint8_t *flags, const double *phi, const dou
               hip_ok(c, hipMemsetAsync(a.res, 0, 16 * B, c->stream), "hipMemset") &&
               hip_ok(c, hipMemsetAsync(a.mex, 0, size_t(a.g.BN) * 8, c->stream), "hipMemset") &&
               hip_ok(c, hipMemsetAsync(a.fo, 0, size_t(a.g.BN) * 18 * sb, c->stream), "hipMemset") &&
-              hip_ok(c, hipMemsetAsync(a.tile_bits, 0, size_t((a.g.BN + 255) / 256 + 31) / 32 * 4, c->stream),
+              hip_ok(c, hipMemsetAsync(a.tile_bits, 0, size_t(tile_count(a.g.BN) + 31) / 32 * 4, c->stream),
                      "hipMemset") &&
               hip_ok(c, hipMemsetAsync(a.claim, 0, size_t(a.g.BN) + 4, c->stream), "hipMemset");
     for (int k = 0; ok && k < 4; ++k)
@@ -486,8 +505,10 @@ bool refresh_bulk_grid(fslbm_ctx *c) {
     if (!hip_ok(c, hipMemcpy(&n, at<int32_t>(c, c->L.cnt) + C_TILES, 4, hipMemcpyDeviceToHost),
                 "hipMemcpy(tile count)"))
         return false;
-    const long long total = ((long long)c->p.nx * c->p.ny * c->p.nz * c->p.batch + 255) / 256;
-    const long long want = std::min<long long>(total, std::max<long long>(1024, 2LL * n));
+    // one wavefront per tile, four per workgroup, room for the list to double
+    const long long total = tile_count((long long)c->p.nx * c->p.ny * c->p.nz * c->p.batch);
+    const long long waves = std::min<long long>(total, std::max<long long>(4096, 2LL * n));
+    const long long want = (waves + 3) / 4;
     if (want > c->bulk_grid) {
         c->bulk_grid = int(want);
         drop_graphs(c);

@@ -221,9 +221,9 @@ struct StepArgs {
     int32_t *list_newg, *list_froml, *list_conv, *list_conv_prev;
     int32_t *list_recv;     // interface cells that receive excess mass this step
     uint8_t *claim;         // [BN] receiver claim bytes, zero between steps
-    int32_t *tiles;        // tiles (256 consecutive cells) that ever held fluid
+    int32_t *tiles;        // tiles (TILE consecutive cells) that ever held fluid
     uint32_t *tile_bits;   // membership bits of that list
-    int bulk_grid;         // workgroups of the bulk kernel (it strides over the tiles)
+    int bulk_grid;         // workgroups of the bulk kernel (its wavefronts stride over the tiles)
     int32_t *cnt;          // device counters, see Counter
     int32_t *nif_dom;      // sharded interface cells per domain (see ND_SHARDS): counted by
                            // the interface kernel, then corrected by the step's conversions
@@ -376,6 +376,13 @@ __device__ __forceinline__ int32_t nif_sum(const int32_t *nif, int p, int B, int
     for (int k = 0; k < ND_SHARDS; ++k) s += nif[(((long long)p * B + b) * ND_SHARDS + k) * 32];
     return s;
 }
+
+// Cells per tile of the bulk kernel's work list: one wavefront's worth of
+// consecutive cells (x fastest), so a wavefront never loads a row it has no
+// fluid in.
+constexpr int TILE = 64;
+constexpr int TILE_SHIFT = 6;
+__host__ __device__ inline long long tile_count(long long BN) { return (BN + TILE - 1) / TILE; }
 
 // Add tile t to the fluid-tile list unless it is there already.
 __device__ __forceinline__ void activate_tile(int32_t *tiles, uint32_t *bits, int32_t *count, int32_t t,

@@ -416,10 +416,11 @@ __device__ __forceinline__ bool update_cell(const StepArgs &a, const long long g
     return marked;
 }
 
-// Bulk kernel: one thread per cell, 256 consecutive cells per tile (x fastest,
-// so every PDF access of a wavefront is a contiguous row segment).  Only tiles
-// that ever held fluid are listed; the workgroups stride over that list, so a
-// mostly empty domain does not pay for its gas.  Liquid cells get the full
+// Bulk kernel: one thread per cell, one wavefront per tile of 64 consecutive
+// cells (x fastest, so every PDF access of a wavefront is a contiguous row
+// segment).  Only tiles that ever held fluid are listed; the wavefronts stride
+// over that list, so a mostly empty domain does not pay for its gas, and a
+// wavefront never loads a row segment without fluid.  Liquid cells get the full
 // stream-collide update.  Interface cells are listed for k_interface in tile
 // order, so the list kernels of the step read neighbouring cells from
 // neighbouring lanes.
@@ -438,10 +439,12 @@ __global__ __launch_bounds__(256) void k_stream_collide(StepArgs a) {
         slist_reset(a.list_mark);
         slist_reset(a.list_if_prev);
     }
-    const int32_t ntiles = int32_t((a.g.BN + 255) / 256);
+    static_assert(TILE == 64, "one tile per wavefront");
+    const int32_t ntiles = int32_t(tile_count(a.g.BN));
     const int32_t nt = min(a.cnt[C_TILES], ntiles);
-    for (int32_t k = blockIdx.x; k < nt; k += gridDim.x) {
-        const long long gid = (long long)a.tiles[k] * 256 + threadIdx.x;
+    const int32_t nw = int32_t(blockDim.x >> 6);
+    for (int32_t k = blockIdx.x * nw + int32_t(threadIdx.x >> 6); k < nt; k += gridDim.x * nw) {
+        const long long gid = ((long long)a.tiles[k] << TILE_SHIFT) + __lane_id();
         const bool valid = gid < a.g.BN;
         const uint8_t fl = valid ? a.flags[gid] : uint8_t(0);
         const bool is_if = (fl & F_IF) != 0;
@@ -493,16 +496,22 @@ __global__ __launch_bounds__(256) void k_interface(StepArgs a) {
 // 1+eps becomes a new interface cell; a cell emptying under -eps next to a
 // filling cell stays interface; liquid next to a remaining emptying cell
 // becomes interface.  Each rule reads only the fill marks, so one pass does all.
-// A second loop clears the marks of the cells converted in the last step.
+// The same pass clears the conversion bit of the cells converted in the last
+// step.
 __global__ __launch_bounds__(256) void k_resolve(StepArgs a) {
     const long long N = a.g.N;
     __shared__ int32_t pref[257];
     const SView marks = slist_view(a.list_mark, pref);
-    FOR_UNIFORM(k, in, marks.total) {
+    // the marks, then the cells converted in the last step (disjoint flag
+    // bits, byte-atomic updates: one index space, side by side)
+    const long long nmk = marks.total, ncp = clamp_cap(a, a.cnt[C_CONV0 + (1 - a.parity)]);
+    FOR_UNIFORM(k, in, nmk + ncp) {
         uint32_t sel_g = 0, sel_l = 0;
         long long cbase = 0;
         int nb[Q];
-        if (in) {
+        if (in && k >= nmk) {
+            flag_clear(a.flags, a.list_conv_prev[k - nmk], F_CONV);
+        } else if (in) {
             const long long gid = sview_at(marks, k);
             const Cell c = decode(a.g, gid);
             cbase = (long long)c.b * N;
@@ -541,10 +550,6 @@ __global__ __launch_bounds__(256) void k_resolve(StepArgs a) {
                            a.cnt + C_NEWG, a.cap, a.cnt + C_ERR);
         wave_append_sel<Q>(sel_l, [&](int i) { return int32_t(cbase + nb[i]); }, a.list_froml,
                            a.cnt + C_FROML, a.cap, a.cnt + C_ERR);
-    }
-    FOR_LIST(k, a.cnt[C_CONV0 + (1 - a.parity)]) {
-        const long long gid = a.list_conv_prev[k];
-        flag_clear(a.flags, gid, F_CONV);
     }
 }
 
@@ -722,8 +727,8 @@ __global__ __launch_bounds__(256) void k_convert(StepArgs a) {
             gid = g0;
             if (active && (t & 31) == 0) {
                 // a new interface cell may sit in a tile that never held fluid
-                activate_tile(a.tiles, a.tile_bits, a.cnt + C_TILES, int32_t(g0 >> 8),
-                              int32_t((a.g.BN + 255) / 256));
+                activate_tile(a.tiles, a.tile_bits, a.cnt + C_TILES, int32_t(g0 >> TILE_SHIFT),
+                              int32_t(tile_count(a.g.BN)));
                 dn = 1;
             }
         } else if (in) {
@@ -844,19 +849,35 @@ __global__ __launch_bounds__(256) void k_excess(StepArgs a) {
     bool spread_any = false;
     for (int b = threadIdx.x; b < a.B; b += blockDim.x) spread_any |= spreads(b);
     spread_any = __syncthreads_or(spread_any);
-    FOR_LIST(k, a.cnt[C_RECV]) {
-        const long long gid = a.list_recv[k];
-        a.claim[gid] = 0;
-        if (!spread_any || !spreads(int(a.g.dN.div(uint32_t(gid))))) receive<ST>(a, gid, 0.0);
-    }
-    // every interface cell after the conversions: its forced filling/emptying
-    // class (Thuerey) from the final neighbour types, and in a domain whose
-    // reservoir is spread its share
     __shared__ int32_t pref[257];
     const SView lst = slist_view(a.list_if, pref);
+    // The three kinds of work items below touch disjoint data, so they share
+    // one index space and run side by side: receivers, then every interface
+    // cell after the conversions (this step's list entries, the new and the
+    // from-liquid cells), then the converted cells.
+    const long long nr = clamp_cap(a, a.cnt[C_RECV]);
     const long long n0 = lst.total, n1 = clamp_cap(a, a.cnt[C_NEWG]), n2 = clamp_cap(a, a.cnt[C_FROML]);
-    for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n0 + n1 + n2;
-         k += (long long)gridDim.x * blockDim.x) {
+    const long long nif = n0 + n1 + n2, ncv = clamp_cap(a, a.cnt[C_CONV0 + p]);
+    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < nr + nif + ncv;
+         t += (long long)gridDim.x * blockDim.x) {
+        if (t < nr) {
+            const long long gid = a.list_recv[t];
+            a.claim[gid] = 0;
+            if (!spread_any || !spreads(int(a.g.dN.div(uint32_t(gid))))) receive<ST>(a, gid, 0.0);
+            continue;
+        }
+        if (t >= nr + nif) {
+            // converted cells: phi in {0, 1} in both fill-level buffers
+            const long long gid = a.list_conv[t - nr - nif];
+            const double v = (a.flags[gid] & F_LIQ) ? 1.0 : 0.0;
+            a.phi_cur[gid] = v;
+            a.phi_next[gid] = v;
+            continue;
+        }
+        // an interface cell after the conversions: its forced filling/emptying
+        // class (Thuerey) from the final neighbour types, and in a domain
+        // whose reservoir is spread its share
+        const long long k = t - nr;
         long long gid;
         if (k < n0) {
             gid = sview_at(lst, k);
@@ -877,12 +898,6 @@ __global__ __launch_bounds__(256) void k_excess(StepArgs a) {
         }
         a.flags[gid] = uint8_t(F_IF | (!has_liq ? F_NOFLUID : (!has_gas ? F_NOEMPTY : 0)));
         if (spread_any && spreads(c.b)) receive<ST>(a, gid, res[c.b] / nif_sum(a.nif_dom, p, a.B, c.b));
-    }
-    FOR_LIST(k, a.cnt[C_CONV0 + p]) {
-        const long long gid = a.list_conv[k];
-        const double v = (a.flags[gid] & F_LIQ) ? 1.0 : 0.0;
-        a.phi_cur[gid] = v;
-        a.phi_next[gid] = v;
     }
 }
 
