@@ -144,7 +144,7 @@ __global__ void k_init_cells(InitArgs ia) {
         // outgoing populations of interface cells, read by the next mass exchange
         typename C::M *fo = static_cast<typename C::M *>(a.fo);
 #pragma unroll
-        for (int i = 1; i < Q; ++i) C::store(fo + (long long)(i - 1) * a.g.BN + gid, typename C::T(d[i]));
+        for (int i = 1; i < Q; ++i) C::store(fo + fo_index(gid, i), typename C::T(d[i]));
     }
     double m = 0.0;
     if (fl == F_IF) {

@@ -200,7 +200,7 @@ constexpr int ND_SHARDS = 64;
 struct StepArgs {
     Geom g;
     void *pdf;
-    void *fo;              // [18][BN] (storage type) outgoing populations f*_i, i = 1..18,
+    void *fo;              // [BN][18] (storage type) outgoing populations f*_i, i = 1..18,
                            // of every interface cell at the end of the last step
     uint8_t *flags;
     double *m;             // [BN] interface mass
@@ -376,6 +376,11 @@ __device__ __forceinline__ int32_t nif_sum(const int32_t *nif, int p, int B, int
     for (int k = 0; k < ND_SHARDS; ++k) s += nif[(((long long)p * B + b) * ND_SHARDS + k) * 32];
     return s;
 }
+
+// Slot of direction i (1..18) in the outgoing-population copy of interface
+// cell gid.  A cell's 18 values are contiguous, so an interface cell costs one
+// or two cache lines wherever the interface cells of a wavefront lie.
+__host__ __device__ inline long long fo_index(long long gid, int i) { return gid * 18 + (i - 1); }
 
 // Cells per tile of the bulk kernel's work list: one wavefront's worth of
 // consecutive cells (x fastest), so a wavefront never loads a row it has no

@@ -69,8 +69,7 @@ __device__ __forceinline__ void store_slot(const StepArgs &a, long long off, dou
 template <int ST>
 __device__ __forceinline__ void store_fo(const StepArgs &a, int i, long long gid, double v) {
     using C = Codec<ST>;
-    C::store(static_cast<typename C::M *>(a.fo) + (long long)(i - 1) * a.g.BN + gid,
-             typename C::T(v));
+    C::store(static_cast<typename C::M *>(a.fo) + fo_index(gid, i), typename C::T(v));
 }
 
 // Shifted post-collision populations of a cell in the given layout.
@@ -277,7 +276,7 @@ __device__ __forceinline__ bool interface_part(const StepArgs &a, const long lon
     uint8_t fn[Q];   // flag of the cell x - c_i (source of direction i)
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-        fo[i] = C::load(fob + (long long)(i - 1) * BN + gid);
+        fo[i] = C::load(fob + fo_index(gid, i));
         fn[i] = src[i] >= 0 ? a.flags[cbase + src[i]] : uint8_t(0);
     }
     const double m0 = a.m[gid];
@@ -411,7 +410,7 @@ __device__ __forceinline__ bool update_cell(const StepArgs &a, const long long g
     if (IF) {
         typename C::M *fob = static_cast<typename C::M *>(a.fo);
 #pragma unroll
-        for (int i = 1; i < Q; ++i) C::store(fob + (long long)(i - 1) * g.BN + gid, d[i]);
+        for (int i = 1; i < Q; ++i) C::store(fob + fo_index(gid, i), d[i]);
     }
     return marked;
 }
