@@ -155,14 +155,19 @@ fslbm_status fslbm_init(const fslbm_params *params, void *workspace, size_t byte
                         fslbm_ctx **out);
 
 /* Enqueue nsteps >= 0 FSLBM time steps (a)-(e) on the context's stream.
- * Asynchronous: device-side failures surface at the next synchronising call. */
+ * Asynchronous: device-side failures surface at the next synchronising call.
+ * Without surface tension, the excess-mass redistribution of each step but
+ * the last runs inside the next step's bulk kernel; the state after the call
+ * is the same. */
 fslbm_status fslbm_step(fslbm_ctx *ctx, int32_t nsteps);
 
 /* Run nsteps >= 1 full time steps (a)-(e) with direct kernel launches and HIP
  * events recorded on the context's stream right before and after the bulk
- * stream-collide kernel of every step.  Synchronises, then returns (HOST
- * doubles, milliseconds) the summed duration of the bulk kernels and the wall
- * time of the whole sequence.  The state advances exactly as fslbm_step. */
+ * stream-collide kernel of every step (which, as in fslbm_step, also runs the
+ * last step's excess-mass redistribution where that is fused).  Synchronises,
+ * then returns (HOST doubles, milliseconds) the summed duration of the bulk
+ * kernels and the wall time of the whole sequence.  The state advances
+ * exactly as fslbm_step. */
 fslbm_status fslbm_step_timed(fslbm_ctx *ctx, int32_t nsteps, double *bulk_ms, double *total_ms);
 
 /* Select the refilling scheme (fslbm_refill) used by subsequent steps. */

@@ -35,6 +35,7 @@ bool make_layout(const fslbm_params &p, Layout &L) {
     L.phi = take(size_t(BN) * 16);   // two buffers
     L.fo = take(size_t(BN) * 18 * storage_bytes(p.storage));
     L.mex = take(size_t(BN) * 8);
+    L.rho_if = take(size_t(BN) * 8);
     bool surf = p.sigma != 0.0;
     L.rhoG = surf ? take(size_t(BN) * 8) : 0;
     L.normal = surf ? take(size_t(BN) * 24) : 0;
@@ -350,6 +351,7 @@ StepArgs make_args(fslbm_ctx *c, int parity) {
     a.phi_next = at<double>(c, c->L.phi) + size_t(1 - parity) * size_t(a.g.BN);
     a.fo = c->ws + c->L.fo;
     a.mex = at<double>(c, c->L.mex);
+    a.rho_if = at<double>(c, c->L.rho_if);
     bool surf = p.sigma != 0.0;
     a.rhoG = surf ? at<double>(c, c->L.rhoG) : nullptr;
     a.normal = surf ? at<double>(c, c->L.normal) : nullptr;
@@ -421,11 +423,13 @@ bool device_errors_ok(fslbm_ctx *c) {
 }
 
 void drop_graphs(fslbm_ctx *c) {
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < 4; ++k)
         if (c->exec[k]) { (void)hipGraphExecDestroy(c->exec[k]); c->exec[k] = nullptr; }
 }
 
-bool capture(fslbm_ctx *c, int parity) {
+// The step graphs hold the step without its own excess-mass redistribution;
+// variant pending = 1 runs the last step's inside the bulk kernel.
+bool capture(fslbm_ctx *c, int parity, int pending) {
     if (!c->cap_stream &&
         !hip_ok(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "hipStreamCreate"))
         return false;
@@ -433,24 +437,36 @@ bool capture(fslbm_ctx *c, int parity) {
     if (!hip_ok(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal),
                 "hipStreamBeginCapture"))
         return false;
-    launch_step(make_args(c, parity), c->p.storage, c->p.collision, c->p.refill, c->cap_stream);
+    const StepArgs prev = make_args(c, 1 - parity);
+    launch_step(make_args(c, parity), c->p.storage, c->p.collision, c->p.refill, c->cap_stream, nullptr,
+                pending ? &prev : nullptr, false);
     hipError_t le = hipGetLastError();
     hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
     if (!hip_ok(c, le, "kernel launch (capture)") || !hip_ok(c, e, "hipStreamEndCapture")) return false;
-    hipError_t ie = hipGraphInstantiate(&c->exec[parity], g, nullptr, nullptr, 0);
+    hipError_t ie = hipGraphInstantiate(&c->exec[parity + 2 * pending], g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     return hip_ok(c, ie, "hipGraphInstantiate");
 }
 
-bool enqueue_step(fslbm_ctx *c) {
+bool enqueue_step(fslbm_ctx *c, bool finish) {
     const int parity = int(c->t & 1);
+    // with surface tension the surface kernels open the next step and read
+    // the redistribution's results: every step finishes
+    finish = finish || c->p.sigma != 0.0;
+    const int pend = c->pending ? 1 : 0;
+    const StepArgs a = make_args(c, parity);
     if (c->graphs) {
-        if (!c->exec[parity] && !capture(c, parity)) return false;
-        if (!hip_ok(c, hipGraphLaunch(c->exec[parity], c->stream), "hipGraphLaunch")) return false;
+        const int v = parity + 2 * pend;
+        if (!c->exec[v] && !capture(c, parity, pend)) return false;
+        if (!hip_ok(c, hipGraphLaunch(c->exec[v], c->stream), "hipGraphLaunch")) return false;
+        if (finish) launch_excess(a, c->p.storage, c->stream);
     } else {
-        launch_step(make_args(c, parity), c->p.storage, c->p.collision, c->p.refill, c->stream);
-        if (!hip_ok(c, hipGetLastError(), "step kernel launch")) return false;
+        const StepArgs prev = make_args(c, 1 - parity);
+        launch_step(a, c->p.storage, c->p.collision, c->p.refill, c->stream, nullptr, pend ? &prev : nullptr,
+                    finish);
     }
+    if (!hip_ok(c, hipGetLastError(), "step kernel launch")) return false;
+    c->pending = !finish;
     ++c->t;
     return true;
 }
@@ -458,6 +474,7 @@ bool enqueue_step(fslbm_ctx *c) {
 bool load_state(fslbm_ctx *c, const uint8_t *flags, const double *phi, const double *rho,
                 const double *u, const double *pdf, const double *mass, const double *reservoir) {
     c->t = 0;
+    c->pending = false;
     StepArgs a = make_args(c, 0);
     const int B = c->p.batch;
     const size_t sb = storage_bytes(c->p.storage);
@@ -606,8 +623,10 @@ fslbm_status fslbm_step(fslbm_ctx *c, int32_t nsteps) {
     if (!c) return FSLBM_EINVAL;
     if (c->status != FSLBM_OK) return c->status;
     if (nsteps < 0) return fail(c, FSLBM_EINVAL, "nsteps must be >= 0");
+    // each step's excess-mass redistribution runs inside the next step's bulk
+    // kernel; the last step finishes its own
     for (int32_t s = 0; s < nsteps; ++s)
-        if (!enqueue_step(c)) return c->status;
+        if (!enqueue_step(c, s + 1 == nsteps)) return c->status;
     return FSLBM_OK;
 }
 
@@ -621,11 +640,19 @@ fslbm_status fslbm_step_timed(fslbm_ctx *c, int32_t nsteps, double *bulk_ms, dou
         if (ok) ok = hip_ok(c, hipEventCreate(&e), "hipEventCreate");
     if (ok) ok = hip_ok(c, hipEventRecord(ev[2 * nsteps], c->stream), "hipEventRecord");
     for (int32_t s = 0; ok && s < nsteps; ++s) {
+        // as fslbm_step: the bulk kernel also runs the last step's excess-mass
+        // redistribution where that is fused
         BulkEvents be{ev[2 * s], ev[2 * s + 1]};
-        launch_step(make_args(c, int(c->t & 1)), c->p.storage, c->p.collision, c->p.refill, c->stream,
-                    &be);
+        const int parity = int(c->t & 1);
+        const bool finish = s + 1 == nsteps || c->p.sigma != 0.0;
+        const StepArgs prev = make_args(c, 1 - parity);
+        launch_step(make_args(c, parity), c->p.storage, c->p.collision, c->p.refill, c->stream, &be,
+                    c->pending ? &prev : nullptr, finish);
         ok = hip_ok(c, hipGetLastError(), "step kernel launch");
-        if (ok) ++c->t;
+        if (ok) {
+            c->pending = !finish;
+            ++c->t;
+        }
     }
     if (ok) ok = hip_ok(c, hipEventRecord(ev[2 * nsteps + 1], c->stream), "hipEventRecord") &&
                  hip_ok(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");

@@ -16,7 +16,7 @@ inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 // Byte offsets of every array inside the caller's workspace.
 struct Layout {
-    size_t pdf, fo, flags, m, phi, mex, rhoG, normal, band;
+    size_t pdf, fo, flags, m, phi, mex, rho_if, rhoG, normal, band;
     size_t lists[5];   // newg, froml, conv0, conv1, recv
     size_t sl_data[4], sl_cnt[4];   // sharded lists: interface (even / odd step), marks, band
     int32_t sl_S, sl_seg, sl_ovf;
@@ -45,7 +45,8 @@ struct fslbm_ctx {
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
     bool graphs = true;
-    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[4] = {nullptr, nullptr, nullptr, nullptr};   // [parity + 2 * pending]
+    bool pending = false;            // the last step's excess-mass redistribution has not run yet
     int bulk_grid = 1024;            // workgroups of the bulk kernel (tile-list stride)
     fslbm::AdjointRun adj;
     fslbm_status status = FSLBM_OK;
@@ -66,8 +67,11 @@ bool hip_ok(fslbm_ctx *c, hipError_t e, const char *what);
 // Check the device error word (the stream must be synchronised).
 bool device_errors_ok(fslbm_ctx *c);
 
-// Enqueue a full FSLBM step on the context's stream (graph replay or direct).
-bool enqueue_step(fslbm_ctx *c);
+// Enqueue a FSLBM step on the context's stream (graph replay or direct).
+// finish = false lets the step end with its excess-mass redistribution
+// pending (without surface tension it then runs inside the next step's bulk
+// kernel); every API call that returns to the caller ends with none pending.
+bool enqueue_step(fslbm_ctx *c, bool finish = true);
 
 // Load a canonical state (device arrays, layouts of fslbm_init) into the
 // context and restart its step count at 0.  reservoir: device [B] or null (0).

@@ -78,6 +78,14 @@ template <> struct Codec<ST_BF16> {
     }
 };
 
+// A value as it reads back after a store in storage type ST.
+template <int ST>
+__device__ __forceinline__ typename Codec<ST>::T codec_round(typename Codec<ST>::T v) {
+    typename Codec<ST>::M m;
+    Codec<ST>::store(&m, v);
+    return Codec<ST>::load(&m);
+}
+
 // ------------------------------------------------------------------ geometry
 // Unsigned division of n < 2^31 by an invariant d >= 1 with one 32x32->64
 // multiply and a shift (Granlund & Montgomery): m = ceil(2^(31+l) / d) with
@@ -208,6 +216,9 @@ struct StepArgs {
     double *phi_next;      // [BN] fill level at the end of this step (the other buffer)
     double *rhoG;          // [BN] gas density at interface cells (sigma != 0), else null
     double *mex;           // [BN] excess mass share of converted cells
+    double *rho_if;        // [BN] density after this step, sum_i f*_i as stored, of every
+                           // interface cell after the conversions (set by its update,
+                           // refill or conversion from liquid; read by the excess step)
     double *normal;        // [3][BN] unit normals on the band (sigma != 0)
     uint32_t *band;        // [ceil(BN/32)] band membership bits (sigma != 0)
     const double *omega;   // [B]

@@ -411,6 +411,11 @@ __device__ __forceinline__ bool update_cell(const StepArgs &a, const long long g
         typename C::M *fob = static_cast<typename C::M *>(a.fo);
 #pragma unroll
         for (int i = 1; i < Q; ++i) C::store(fob + fo_index(gid, i), d[i]);
+        // the density after this step as a read-back of the stored populations sums it
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) s += double(codec_round<ST>(d[i]));
+        a.rho_if[gid] = 1.0 + s;
     }
     return marked;
 }
@@ -423,33 +428,35 @@ __device__ __forceinline__ bool update_cell(const StepArgs &a, const long long g
 // stream-collide update.  Interface cells are listed for k_interface in tile
 // order, so the list kernels of the step read neighbouring cells from
 // neighbouring lanes.
+// Cell types are read through type_after: with the last step's excess-mass
+// work running in the same grid, a new interface cell may still carry its
+// gas-typed flag while this kernel reads it.
 template <int ST, int COLL, int PAR>
-__global__ __launch_bounds__(256) void k_stream_collide(StepArgs a) {
+__device__ __forceinline__ void bulk_part(const StepArgs &a, const int wg, const int nwg) {
     const int p = a.parity;
-    if (blockIdx.x == 0) {
-        // this step's lists start empty (the last step's lengths stayed
-        // readable until now); the next step's interface list too
-        if (threadIdx.x == 0) {
-            a.cnt[C_NEWG] = 0;
-            a.cnt[C_FROML] = 0;
-            a.cnt[C_CONV0 + p] = 0;
-            a.cnt[C_RECV] = 0;
-        }
+    if (wg == 0) {
+        // this step's conversion and mark lists start empty (the other lists
+        // are cleared by k_interface, after the last step's excess work)
+        if (threadIdx.x == 0) a.cnt[C_CONV0 + p] = 0;
         slist_reset(a.list_mark);
-        slist_reset(a.list_if_prev);
     }
     static_assert(TILE == 64, "one tile per wavefront");
     const int32_t ntiles = int32_t(tile_count(a.g.BN));
     const int32_t nt = min(a.cnt[C_TILES], ntiles);
     const int32_t nw = int32_t(blockDim.x >> 6);
-    for (int32_t k = blockIdx.x * nw + int32_t(threadIdx.x >> 6); k < nt; k += gridDim.x * nw) {
+    for (int32_t k = wg * nw + int32_t(threadIdx.x >> 6); k < nt; k += nwg * nw) {
         const long long gid = ((long long)a.tiles[k] << TILE_SHIFT) + __lane_id();
         const bool valid = gid < a.g.BN;
         const uint8_t fl = valid ? a.flags[gid] : uint8_t(0);
-        const bool is_if = (fl & F_IF) != 0;
-        if (fl & F_LIQ) update_cell<ST, COLL, PAR, false>(a, gid, fl);
-        slist_append(a.list_if, is_if, int32_t(gid), a.cnt + C_ERR);
+        const uint8_t ty = type_after(fl);
+        if (ty == F_LIQ) update_cell<ST, COLL, PAR, false>(a, gid, fl);
+        slist_append(a.list_if, ty == F_IF, int32_t(gid), a.cnt + C_ERR);
     }
+}
+
+template <int ST, int COLL, int PAR>
+__global__ __launch_bounds__(256) void k_stream_collide(StepArgs a) {
+    bulk_part<ST, COLL, PAR>(a, int(blockIdx.x), int(gridDim.x));
 }
 
 // Add v (per lane) to the sharded interface count of the lane's domain; one
@@ -475,6 +482,17 @@ __device__ __forceinline__ void count_interface(const StepArgs &a, int v, long l
 // anti-bounce-back, fill level and conversion marks; marked cells are listed.
 template <int ST, int COLL, int PAR>
 __global__ __launch_bounds__(256) void k_interface(StepArgs a) {
+    if (blockIdx.x == 0) {
+        // the conversion lists of this step start empty (the last step's
+        // stayed readable through its excess work); the next step's interface
+        // list too
+        if (threadIdx.x == 0) {
+            a.cnt[C_NEWG] = 0;
+            a.cnt[C_FROML] = 0;
+            a.cnt[C_RECV] = 0;
+        }
+        slist_reset(a.list_if_prev);
+    }
     __shared__ int32_t pref[257];
     const SView lst = slist_view(a.list_if, pref);
     FOR_UNIFORM(k, in, lst.total) {
@@ -680,7 +698,16 @@ __device__ __forceinline__ void refill_group(const StepArgs &a, const long long 
     if (active && lane < Q) {
         store_slot<ST>(a, slot_flat_rt(a.g, layoutB, c, i), out);
         if (i > 0) store_fo<ST>(a, i, gid, out);
-        if (lane == 0) a.m[gid] = 0.0;
+    }
+    // density after this step: the stored populations summed in direction order
+    const double rt = lane < Q ? double(codec_round<ST>(typename Codec<ST>::T(out))) : 0.0;
+    const int gl = __lane_id() & 32;
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) s += __shfl(rt, gl + k);
+    if (active && lane == 0) {
+        a.m[gid] = 0.0;
+        a.rho_if[gid] = 1.0 + s;
     }
 }
 
@@ -774,7 +801,9 @@ __global__ __launch_bounds__(256) void k_convert(StepArgs a) {
             } else {
                 // from liquid: mass = density; keep a copy of its populations
                 double d[Q];
-                a.m[gid] = rho_after<ST>(a, c, d);
+                const double rho = rho_after<ST>(a, c, d);
+                a.m[gid] = rho;
+                a.rho_if[gid] = rho;
 #pragma unroll
                 for (int i = 1; i < Q; ++i) store_fo<ST>(a, i, gid, d[i]);
                 a.flags[gid] = F_IF;
@@ -816,9 +845,8 @@ __device__ __forceinline__ void receive(const StepArgs &a, long long gid, double
         touched = true;
     }
     if (touched) {
-        double d[Q];
         a.m[gid] = m;
-        a.phi_next[gid] = m / rho_after<ST>(a, c, d);
+        a.phi_next[gid] = m / a.rho_if[gid];
     }
 }
 
@@ -828,15 +856,17 @@ __device__ __forceinline__ void receive(const StepArgs &a, long long gid, double
 // the from-liquid cells) gets its type and forced class, and in a domain whose
 // reservoir is spread its share of it (receivers of such a domain are left to
 // this loop).  Converted cells get phi in {0, 1} in both fill-level buffers.
-// Block 0 carries the reservoir over and resets the counters the next step
-// needs at zero.
+// Workgroup 0 carries the reservoir over and clears the interface counts the
+// next step accumulates.  wg / nwg: this workgroup's index among the nwg
+// workgroups that share the work (the whole grid, or a part of the next
+// step's bulk grid).
 template <int ST>
-__global__ __launch_bounds__(256) void k_excess(StepArgs a) {
+__device__ __forceinline__ void excess_part(const StepArgs &a, const int wg, const int nwg) {
     const int p = a.parity;
     const double *res = a.res + p * a.B;
     // the reservoir is spread when it holds mass and the domain has interface cells
     auto spreads = [&](int b) { return res[b] != 0.0 && nif_sum(a.nif_dom, p, a.B, b) > 0; };
-    if (blockIdx.x == 0) {
+    if (wg == 0) {
         for (int b = threadIdx.x; b < a.B; b += blockDim.x) {
             // mass that found no receiver is kept while the domain has no interface
             a.res[(1 - p) * a.B + b] = spreads(b) ? 0.0 : res[b];
@@ -857,8 +887,8 @@ __global__ __launch_bounds__(256) void k_excess(StepArgs a) {
     const long long nr = clamp_cap(a, a.cnt[C_RECV]);
     const long long n0 = lst.total, n1 = clamp_cap(a, a.cnt[C_NEWG]), n2 = clamp_cap(a, a.cnt[C_FROML]);
     const long long nif = n0 + n1 + n2, ncv = clamp_cap(a, a.cnt[C_CONV0 + p]);
-    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < nr + nif + ncv;
-         t += (long long)gridDim.x * blockDim.x) {
+    for (long long t = (long long)wg * blockDim.x + threadIdx.x; t < nr + nif + ncv;
+         t += (long long)nwg * blockDim.x) {
         if (t < nr) {
             const long long gid = a.list_recv[t];
             a.claim[gid] = 0;
@@ -900,6 +930,29 @@ __global__ __launch_bounds__(256) void k_excess(StepArgs a) {
     }
 }
 
+template <int ST>
+__global__ __launch_bounds__(256) void k_excess(StepArgs a) {
+    excess_part<ST>(a, int(blockIdx.x), int(gridDim.x));
+}
+
+// Workgroups of the last step's excess-mass work ahead of the bulk grid.
+constexpr int EXCESS_WG = 256;
+
+// The bulk kernel of this step (a) fused with the excess-mass work of the last
+// step (ae).  The two touch disjoint data: the excess work writes mass, fill
+// levels, the flag bytes of interface cells (type-preserving) and its own
+// counters; the bulk work writes the populations of liquid cells only (every
+// cell's slot set is its own).  Its latency-bound chains overlap the
+// bandwidth-bound bulk instead of running as a kernel of their own.
+template <int ST, int COLL, int PAR>
+__global__ __launch_bounds__(256) void k_excess_stream_collide(StepArgs a, StepArgs ae) {
+    if (blockIdx.x < EXCESS_WG)
+        excess_part<ST>(ae, int(blockIdx.x), EXCESS_WG);
+    else
+        bulk_part<ST, COLL, PAR>(a, int(blockIdx.x) - EXCESS_WG, int(gridDim.x) - EXCESS_WG);
+}
+
+
 // ------------------------------------------------------------------ launchers
 
 // List kernels get a fixed grid (the list lengths are only known on the
@@ -914,10 +967,23 @@ static void launch_bulk(K kernel, const StepArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(kernel, dim3(unsigned(a.bulk_grid)), dim3(256), 0, s, a);
 }
 
+template <int ST, int COLL, int PAR>
+static void launch_bulk_t(const StepArgs &a, const StepArgs *pending, hipStream_t s) {
+    if (pending)
+        hipLaunchKernelGGL((k_excess_stream_collide<ST, COLL, PAR>), dim3(unsigned(EXCESS_WG + a.bulk_grid)),
+                           dim3(256), 0, s, a, *pending);
+    else
+        launch_bulk(k_stream_collide<ST, COLL, PAR>, a, s);
+}
+
 template <int ST>
 static void launch_step_t(const StepArgs &a, int collision, int scheme, hipStream_t s,
-                          const BulkEvents *ev) {
+                          const BulkEvents *ev, const StepArgs *pending, bool finish) {
     const int lb = list_blocks(a.cap);
+    if (pending && a.rhoG) {
+        hipLaunchKernelGGL(k_excess<ST>, dim3(lb), dim3(256), 0, s, *pending);
+        pending = nullptr;
+    }
     if (a.rhoG) {
         hipLaunchKernelGGL(k_band, dim3(lb), dim3(256), 0, s, a);
         hipLaunchKernelGGL(k_normals, dim3(lb), dim3(256), 0, s, a);
@@ -925,11 +991,11 @@ static void launch_step_t(const StepArgs &a, int collision, int scheme, hipStrea
     }
     if (ev) (void)hipEventRecord(ev->before, s);
     if (collision == 0) {
-        if (a.parity == 0) launch_bulk(k_stream_collide<ST, 0, 0>, a, s);
-        else launch_bulk(k_stream_collide<ST, 0, 1>, a, s);
+        if (a.parity == 0) launch_bulk_t<ST, 0, 0>(a, pending, s);
+        else launch_bulk_t<ST, 0, 1>(a, pending, s);
     } else {
-        if (a.parity == 0) launch_bulk(k_stream_collide<ST, 1, 0>, a, s);
-        else launch_bulk(k_stream_collide<ST, 1, 1>, a, s);
+        if (a.parity == 0) launch_bulk_t<ST, 1, 0>(a, pending, s);
+        else launch_bulk_t<ST, 1, 1>(a, pending, s);
     }
     if (ev) (void)hipEventRecord(ev->after, s);
     if (collision == 0) {
@@ -947,7 +1013,7 @@ static void launch_step_t(const StepArgs &a, int collision, int scheme, hipStrea
         case 3: hipLaunchKernelGGL((k_convert<ST, 3>), dim3(lb), dim3(256), 0, s, a); break;
         default: hipLaunchKernelGGL((k_convert<ST, 4>), dim3(lb), dim3(256), 0, s, a); break;
     }
-    hipLaunchKernelGGL(k_excess<ST>, dim3(lb), dim3(256), 0, s, a);
+    if (finish) hipLaunchKernelGGL(k_excess<ST>, dim3(lb), dim3(256), 0, s, a);
 }
 
 }  // namespace
@@ -955,19 +1021,32 @@ static void launch_step_t(const StepArgs &a, int collision, int scheme, hipStrea
 #if defined(FSLBM_UNIT_STORAGE)
 template <>
 void launch_step_storage<FSLBM_UNIT_STORAGE>(const StepArgs &a, int collision, int scheme,
-                                             hipStream_t s, const BulkEvents *ev) {
-    launch_step_t<FSLBM_UNIT_STORAGE>(a, collision, scheme, s, ev);
+                                             hipStream_t s, const BulkEvents *ev,
+                                             const StepArgs *pending, bool finish) {
+    launch_step_t<FSLBM_UNIT_STORAGE>(a, collision, scheme, s, ev, pending, finish);
+}
+template <>
+void launch_excess_storage<FSLBM_UNIT_STORAGE>(const StepArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(k_excess<FSLBM_UNIT_STORAGE>, dim3(list_blocks(a.cap)), dim3(256), 0, s, a);
 }
 #endif
 
 #if defined(FSLBM_UNIT_DISPATCH)
 void launch_step(const StepArgs &a, int storage, int collision, int scheme, hipStream_t s,
-                 const BulkEvents *ev) {
+                 const BulkEvents *ev, const StepArgs *pending, bool finish) {
     switch (storage) {
-        case ST_F64: launch_step_storage<ST_F64>(a, collision, scheme, s, ev); break;
-        case ST_F32: launch_step_storage<ST_F32>(a, collision, scheme, s, ev); break;
-        case ST_F16: launch_step_storage<ST_F16>(a, collision, scheme, s, ev); break;
-        default: launch_step_storage<ST_BF16>(a, collision, scheme, s, ev); break;
+        case ST_F64: launch_step_storage<ST_F64>(a, collision, scheme, s, ev, pending, finish); break;
+        case ST_F32: launch_step_storage<ST_F32>(a, collision, scheme, s, ev, pending, finish); break;
+        case ST_F16: launch_step_storage<ST_F16>(a, collision, scheme, s, ev, pending, finish); break;
+        default: launch_step_storage<ST_BF16>(a, collision, scheme, s, ev, pending, finish); break;
+    }
+}
+void launch_excess(const StepArgs &a, int storage, hipStream_t s) {
+    switch (storage) {
+        case ST_F64: launch_excess_storage<ST_F64>(a, s); break;
+        case ST_F32: launch_excess_storage<ST_F32>(a, s); break;
+        case ST_F16: launch_excess_storage<ST_F16>(a, s); break;
+        default: launch_excess_storage<ST_BF16>(a, s); break;
     }
 }
 #endif
