@@ -21,6 +21,12 @@ cpu_baseline  the FP64 CPU oracle (single thread) on a bounded sample of the
            same workload.
 variants   other storage types, the dense pool-wave case (83% fluid), and the
            reduced-precision error against the FP64 run.
+wave_frequency  the Sec. 4.1 gravity wave at L = 400 in every storage type.
+dam_break  rectangular dam break 256 x 128 x 64 (FP32), each refilling scheme,
+           20000 steps: front position, residual height, stability, mass drift.
+drop_impact  drop impact 256^3 with surface tension, every storage type, 8000
+           steps: centre-column height, cavity depth, mass drift, and the
+           fill-level / flag differences against the FP64 run.
 """
 from __future__ import annotations
 
@@ -141,6 +147,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--variant-steps", type=int, default=300)
+    ap.add_argument("--no-reports", action="store_true",
+                    help="skip the rectangular dam break and drop impact reports")
+    ap.add_argument("--dam-break-steps", type=int, default=20000)
+    ap.add_argument("--drop-steps", type=int, default=8000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB elementwise copy kernel 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -201,6 +211,9 @@ def main():
     if not args.no_variants:
         result["variants"] = variants(fslbm, setups, torch, args)
         result["wave_frequency"] = wave_frequency(fslbm)
+    if not args.no_reports:
+        result["dam_break"] = dam_break_report(fslbm, setups, torch, args.dam_break_steps)
+        result["drop_impact"] = drop_impact_report(fslbm, setups, torch, args.drop_steps)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
         result["cpu_baseline"] = cpu_baseline(setup)
@@ -226,6 +239,98 @@ def wave_frequency(fslbm, L=400, t_star_end=10.0):
         out.append(rec)
         log(f"  gravity wave L={L} {name}: T*/2 = {rec['half_periods']}")
     return out
+
+
+def dam_break_report(fslbm, setups, torch, steps, every=1000):
+    """Rectangular dam break 256x128x64 (FP32 storage), each refilling scheme:
+    front position and residual height every `every` steps in cells and in the
+    paper's dimensionless form (w* = front / W, h* = height / H, t* = t sqrt(2 g / W),
+    Sec. 4.2), the first check at which the run was unstable, and the mass drift."""
+    import math
+    from paper_2207_14496_amd import observe
+    out = []
+    for scheme, name in enumerate(("EQ", "EQ+NEQ", "GEQ", "EXT", "AVG")):
+        s = setups.rect_dam_break(refill=scheme)
+        W, H, g = s.meta["width"], s.meta["height"], abs(s.g[2])
+        sim = fslbm.from_setup(s, storage=fslbm.F32)
+        m0 = sim.diagnostics()[0]["total_mass"]
+        series, unstable_at, done, t0 = [], None, 0, time.perf_counter()
+        while done < steps:
+            k = min(every, steps - done)
+            sim.step(k)
+            done += k
+            d = sim.diagnostics()[0]
+            if not d["stable"]:
+                unstable_at = done
+                break
+            fl = sim.read(("flags",))["flags"][0]
+            xf = observe.front_position(fl, s.nx, s.ny, s.nz)
+            hz = observe.residual_height(fl, s.nx, s.ny, s.nz)
+            series.append([done, round(done * math.sqrt(2 * g / W), 4), xf, round(xf / W, 4), hz,
+                           round(hz / H, 4)])
+        el = time.perf_counter() - t0
+        rec = {"scheme": name, "steps_run": done, "first_unstable_check": unstable_at,
+               "mass_drift_rel": (d["total_mass"] - m0) / m0 if unstable_at is None else None,
+               "series": series, "series_columns": ["step", "t*", "front_cells", "w*",
+                                                     "height_cells", "h*"],
+               "wall_s": round(el, 2)}
+        sim.close()
+        torch.cuda.empty_cache()
+        out.append(rec)
+        last = series[-1] if series else None
+        log(f"  dam break {name}: {done} steps, unstable at {unstable_at}, last {last}")
+    return {"workload": "rect-dam-break 256x128x64 D3Q19 TRT omega=1.95 g=2e-5, f32 shifted PDFs",
+            "schemes": out}
+
+
+def drop_impact_report(fslbm, setups, torch, steps, every=1000):
+    """Drop impact 256^3 with surface tension (sigma = 1e-4), EQ refilling, in
+    every storage type: centre-column liquid height and cavity depth below the
+    initial surface every `every` steps, mass drift, and the fill-level and
+    flag differences against the FP64 run at the end."""
+    from paper_2207_14496_amd import observe
+    s = setups.drop_impact()
+    n, depth = s.nx, s.meta["pool_depth"]
+    c = n // 2
+    out, ref = [], None
+    for name, st in (("f64", fslbm.F64), ("f32", fslbm.F32), ("f16", fslbm.F16), ("bf16", fslbm.BF16)):
+        sim = fslbm.from_setup(s, storage=st)
+        m0 = sim.diagnostics()[0]["total_mass"]
+        series, done, unstable_at = [], 0, None
+        t0 = time.perf_counter()
+        while done < steps:
+            k = min(every, steps - done)
+            sim.step(k)
+            done += k
+            d = sim.diagnostics()[0]
+            if not d["stable"]:
+                unstable_at = done
+                break
+            phi = sim.read(("phi",))["phi"][0]
+            series.append([done, round(observe.column_height(phi, n, n, n, c, c), 4),
+                           round(observe.cavity_depth(phi, n, n, n, c, c, depth), 2)])
+        el = time.perf_counter() - t0
+        rec = {"storage": name, "steps_run": done, "first_unstable_check": unstable_at,
+               "ms_per_step": round(el * 1e3 / max(done, 1), 4),
+               "mass_drift_rel": (d["total_mass"] - m0) / m0,
+               "series": series, "series_columns": ["step", "centre_column_height", "cavity_depth"]}
+        f = sim.read(("phi", "flags"))
+        if ref is None:
+            ref = {"phi": f["phi"][0].clone(), "flags": f["flags"][0].clone(), "series": series}
+        else:
+            dphi = (f["phi"][0] - ref["phi"]).abs()
+            rec["vs_f64"] = {"l1_phi": float(dphi.mean()), "max_abs_phi": float(dphi.max()),
+                             "flag_mismatch_cells": int((f["flags"][0] != ref["flags"]).sum()),
+                             "max_abs_centre_height": max((abs(a[1] - b[1]) for a, b in
+                                                           zip(series, ref["series"])), default=None)}
+        sim.close()
+        del f
+        torch.cuda.empty_cache()
+        out.append(rec)
+        log(f"  drop impact {name}: {done} steps, {rec['ms_per_step']} ms/step, "
+            f"last {series[-1] if series else None}, vs f64 {rec.get('vs_f64')}")
+    return {"workload": "drop-impact 256^3 D3Q19 TRT omega=1.989 sigma=1e-4 g=1e-6 EQ refill",
+            "runs": out}
 
 
 def variants(fslbm, setups, torch, args):
