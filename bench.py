@@ -22,6 +22,8 @@ cpu_baseline  the FP64 CPU oracle (single thread) on a bounded sample of the
 variants   other storage types, the dense pool-wave case (83% fluid), and the
            reduced-precision error against the FP64 run.
 wave_frequency  the Sec. 4.1 gravity wave at L = 400 in every storage type.
+gravity_wave_schemes  the same wave at L = 800 (FP64) with each refilling
+           scheme, next to the per-scheme series the paper prints.
 dam_break  rectangular dam break 256 x 128 x 64 (FP32), each refilling scheme,
            20000 steps: front position, residual height, stability, mass drift.
 drop_impact  drop impact 256^3 with surface tension, every storage type, 8000
@@ -212,6 +214,7 @@ def main():
         result["variants"] = variants(fslbm, setups, torch, args)
         result["wave_frequency"] = wave_frequency(fslbm)
     if not args.no_reports:
+        result["gravity_wave_schemes"] = gravity_wave_schemes(fslbm)
         result["dam_break"] = dam_break_report(fslbm, setups, torch, args.dam_break_steps)
         result["drop_impact"] = drop_impact_report(fslbm, setups, torch, args.drop_steps)
     if not args.no_cpu_baseline:
@@ -238,6 +241,33 @@ def wave_frequency(fslbm, L=400, t_star_end=10.0):
             rec["rel_err_vs_f64"] = [round(v / r - 1, 6) for v, r in zip(hp, ref)]
         out.append(rec)
         log(f"  gravity wave L={L} {name}: T*/2 = {rec['half_periods']}")
+    return out
+
+
+def gravity_wave_schemes(fslbm, L=800, t_star_end=15.0):
+    """Sec. 4.1 gravity wave at the paper's resolution L = 800 (FP64) with each
+    refilling scheme: the first four half-periods T*/2 and the first
+    logarithmic decrement, next to the series the paper prints for the same
+    scheme (tests/golden/gravity_wave_sec41.json)."""
+    from paper_2207_14496_amd import waves
+    with open(os.path.join(ROOT, "tests", "golden", "gravity_wave_sec41.json")) as fh:
+        paper = json.load(fh)["schemes_L800"]
+    out = []
+    for scheme, name in enumerate(("EQ", "EQ+NEQ", "GEQ", "EXT", "AVG")):
+        t0 = time.perf_counter()
+        t, a, _, diag = waves.run(L, fslbm.F64, t_star_end=t_star_end, every=80, refill=scheme)
+        hp = [float(v) for v in waves.half_periods(t, a)[:4]]
+        ld = waves.log_decrements(t, a)[:1]
+        ref = paper[name]
+        rec = {"scheme": name, "L": L, "half_periods": [round(v, 4) for v in hp],
+               "paper_half_periods": [round(v, 4) for v in ref["half_period"][:len(hp)]],
+               "rel_diff_vs_paper": [round(v / r - 1, 4) for v, r in zip(hp, ref["half_period"])],
+               "log_decrement": [[round(x, 3), round(dl, 4)] for x, dl in ld],
+               "paper_log_decrement": [[round(x, 3), round(dl, 4)] for x, dl in ref.get("log_decrement", [])[:1]],
+               "stable": bool(diag["finite"]), "wall_s": round(time.perf_counter() - t0, 1)}
+        out.append(rec)
+        log(f"  gravity wave L={L} {name}: T*/2 {rec['half_periods']} (paper {rec['paper_half_periods']}), "
+            f"delta {rec['log_decrement']} (paper {rec['paper_log_decrement']})")
     return out
 
 
