@@ -22,8 +22,8 @@ cpu_baseline  the FP64 CPU oracle (single thread) on a bounded sample of the
 variants   other storage types, the dense pool-wave case (83% fluid), and the
            reduced-precision error against the FP64 run.
 wave_frequency  the Sec. 4.1 gravity wave at L = 400 in every storage type.
-gravity_wave_schemes  the same wave at L = 800 (FP64) with each refilling
-           scheme, next to the per-scheme series the paper prints.
+gravity_wave_schemes  (--gravity-wave-schemes) the same wave at L = 800 (FP64)
+           with each refilling scheme, next to the per-scheme series the paper prints.
 dam_break  rectangular dam break 256 x 128 x 64 (FP32), each refilling scheme,
            20000 steps: front position, residual height, stability, mass drift.
 drop_impact  drop impact 256^3 with surface tension, every storage type, 8000
@@ -152,6 +152,8 @@ def main():
     ap.add_argument("--no-reports", action="store_true",
                     help="skip the rectangular dam break and drop impact reports")
     ap.add_argument("--dam-break-steps", type=int, default=20000)
+    ap.add_argument("--gravity-wave-schemes", action="store_true",
+                    help="also run the L = 800 gravity wave with every refilling scheme (about 3 min)")
     ap.add_argument("--drop-steps", type=int, default=8000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB elementwise copy kernel 5 times (HBM counter calibration)")
@@ -213,8 +215,9 @@ def main():
     if not args.no_variants:
         result["variants"] = variants(fslbm, setups, torch, args)
         result["wave_frequency"] = wave_frequency(fslbm)
-    if not args.no_reports:
+    if args.gravity_wave_schemes:
         result["gravity_wave_schemes"] = gravity_wave_schemes(fslbm)
+    if not args.no_reports:
         result["dam_break"] = dam_break_report(fslbm, setups, torch, args.dam_break_steps)
         result["drop_impact"] = drop_impact_report(fslbm, setups, torch, args.drop_steps)
     if not args.no_cpu_baseline:
