@@ -409,20 +409,21 @@ __device__ __forceinline__ void activate_tile(int32_t *tiles, uint32_t *bits, in
     if (pos < ntiles) tiles[pos] = t;
 }
 
-// Byte-granular atomic OR on the flag array (4-byte aligned, padded).
-// Returns the previous byte value.
+// Byte-granular atomic OR on a byte array whose base is 4-byte aligned (the
+// workspace arrays are 256-byte aligned) and padded to whole words.  Returns
+// the previous byte value.  The word is addressed by pointer arithmetic on
+// the array itself, so the compiler keeps the global address space (global,
+// not flat, atomics: several can be in flight at once).
 __device__ __forceinline__ uint8_t flag_or(uint8_t *flags, long long i, uint8_t bits) {
-    uintptr_t a = reinterpret_cast<uintptr_t>(flags + i);
-    unsigned int *w = reinterpret_cast<unsigned int *>(a & ~uintptr_t(3));
-    int sh = int(a & 3) * 8;
-    unsigned int old = atomicOr(w, (unsigned int)bits << sh);
+    unsigned int *w = reinterpret_cast<unsigned int *>(flags + (i & ~3LL));
+    const int sh = int(i & 3) * 8;
+    const unsigned int old = atomicOr(w, (unsigned int)bits << sh);
     return uint8_t(old >> sh);
 }
-// Byte-granular atomic clear of `bits`.
+// Byte-granular atomic clear of `bits` (same layout rules).
 __device__ __forceinline__ void flag_clear(uint8_t *flags, long long i, uint8_t bits) {
-    uintptr_t a = reinterpret_cast<uintptr_t>(flags + i);
-    unsigned int *w = reinterpret_cast<unsigned int *>(a & ~uintptr_t(3));
-    int sh = int(a & 3) * 8;
+    unsigned int *w = reinterpret_cast<unsigned int *>(flags + (i & ~3LL));
+    const int sh = int(i & 3) * 8;
     atomicAnd(w, ~((unsigned int)bits << sh));
 }
 

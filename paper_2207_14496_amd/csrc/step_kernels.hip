@@ -537,14 +537,14 @@ __global__ __launch_bounds__(256) void k_resolve(StepArgs a) {
             uint8_t fn[Q];
 #pragma unroll
             for (int i = 1; i < Q; ++i) fn[i] = a.flags[cbase + (nb[i] >= 0 ? nb[i] : c.n)];
+            // the neighbours to mark (gas next to a filling cell, liquid next
+            // to an emptying cell that no filling neighbour cancels)
+            uint8_t bit = 0;
+            uint32_t tmask = 0;
             if (fl & F_MARK_A) {
-                uint8_t old[Q];
+                bit = F_MARK_A;
 #pragma unroll
-                for (int i = 1; i < Q; ++i)
-                    old[i] = (nb[i] >= 0 && (fn[i] & F_GAS)) ? flag_or(a.flags, cbase + nb[i], F_MARK_A)
-                                                            : F_MARK_A;
-#pragma unroll
-                for (int i = 1; i < Q; ++i) sel_g |= (old[i] & F_MARK_A) ? 0u : (1u << i);
+                for (int i = 1; i < Q; ++i) tmask |= (nb[i] >= 0 && (fn[i] & F_GAS)) ? (1u << i) : 0u;
             } else if (fl & F_MARK_B) {
                 bool near_fill = false;
 #pragma unroll
@@ -553,14 +553,26 @@ __global__ __launch_bounds__(256) void k_resolve(StepArgs a) {
                 if (near_fill) {
                     flag_clear(a.flags, gid, F_MARK_B);
                 } else {
-                    uint8_t old[Q];
+                    bit = F_MARK_B;
 #pragma unroll
-                    for (int i = 1; i < Q; ++i)
-                        old[i] = (nb[i] >= 0 && (fn[i] & F_LIQ)) ? flag_or(a.flags, cbase + nb[i], F_MARK_B)
-                                                                : F_MARK_B;
-#pragma unroll
-                    for (int i = 1; i < Q; ++i) sel_l |= (old[i] & F_MARK_B) ? 0u : (1u << i);
+                    for (int i = 1; i < Q; ++i) tmask |= (nb[i] >= 0 && (fn[i] & F_LIQ)) ? (1u << i) : 0u;
                 }
+            }
+            if (bit) {
+                // one atomic per direction, issued without branches so that all
+                // are in flight together (an OR of 0 where there is nothing to
+                // mark); a cell is listed by the lane that set its mark
+                uint8_t old[Q];
+#pragma unroll
+                for (int i = 1; i < Q; ++i) {
+                    const bool t = (tmask >> i) & 1u;
+                    old[i] = flag_or(a.flags, nb[i] >= 0 ? cbase + nb[i] : gid, t ? bit : uint8_t(0));
+                }
+                uint32_t sel = 0;
+#pragma unroll
+                for (int i = 1; i < Q; ++i) sel |= (((tmask >> i) & 1u) && !(old[i] & bit)) ? (1u << i) : 0u;
+                if (bit == F_MARK_A) sel_g = sel;
+                else sel_l = sel;
             }
         }
         wave_append_sel<Q>(sel_g, [&](int i) { return int32_t(cbase + nb[i]); }, a.list_newg,
@@ -782,16 +794,16 @@ __global__ __launch_bounds__(256) void k_convert(StepArgs a) {
                         a.mex[gid] = 0.0;
                     } else {
                         a.mex[gid] = mx / nr;
-                        // claim the receivers (each is listed once)
+                        // claim the receivers (each is listed once); one atomic
+                        // per direction without branches, as in k_resolve
+                        uint8_t old[Q];
 #pragma unroll
-                        for (int i = 1; i < Q; ++i) {
-                            if (!((recv >> i) & 1u)) continue;
-                            const long long q = cbase + nb[i];
-                            uintptr_t ad = reinterpret_cast<uintptr_t>(a.claim + q);
-                            unsigned int *w = reinterpret_cast<unsigned int *>(ad & ~uintptr_t(3));
-                            const unsigned int bit = 1u << (int(ad & 3) * 8);
-                            if (!(atomicOr(w, bit) & bit)) sel |= 1u << i;
-                        }
+                        for (int i = 1; i < Q; ++i)
+                            old[i] = flag_or(a.claim, nb[i] >= 0 ? cbase + nb[i] : gid,
+                                             ((recv >> i) & 1u) ? uint8_t(1) : uint8_t(0));
+#pragma unroll
+                        for (int i = 1; i < Q; ++i)
+                            sel |= (((recv >> i) & 1u) && !(old[i] & 1)) ? (1u << i) : 0u;
                     }
                     a.flags[gid] = uint8_t((fill ? F_LIQ : F_GAS) | F_CONV);
                     a.m[gid] = 0.0;
