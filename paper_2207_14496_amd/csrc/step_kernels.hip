@@ -48,6 +48,11 @@ namespace {   // every kernel has internal linkage; only the launchers are expor
          k##_it < k##_n; ++k##_it, k += k##_str)                                       \
         if (const bool in = k < k##_end; true)
 
+// Keeps the loads issued above it from being moved below it (into the
+// branches that use them), so that they are all in flight at once.  Emits no
+// instruction and no wait.
+__device__ __forceinline__ void issue_fence() { asm volatile("" ::: "memory"); }
+
 __device__ __forceinline__ long long clamp_cap(const StepArgs &a, int32_t v) {
     return v < a.cap ? (long long)v : a.cap;
 }
@@ -283,6 +288,15 @@ __device__ __forceinline__ bool interface_part(const StepArgs &a, const long lon
     const double phx = a.phi_cur[gid];
     // mass exchange: the neighbour x + c_i is the source of direction opp(i)
     const int cc = fclass(fl);
+    // fill levels of the interface neighbours, all loads in flight together
+    // (the cell's own where the neighbour is not interface; unused there)
+    double phn[Q];
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const int o = opp(i);
+        const bool itf = src[o] >= 0 && !(fn[o] & (F_GAS | F_LIQ));
+        phn[i] = a.phi_cur[itf ? cbase + src[o] : gid];
+    }
     double dm = 0.0;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
@@ -295,8 +309,7 @@ __device__ __forceinline__ bool interface_part(const StepArgs &a, const long lon
         if (f & F_LIQ) {
             dm += fin - fout;
         } else {
-            const double phn = a.phi_cur[cbase + src[o]];
-            dm += 0.5 * (phx + phn) * link_flux(cc, fclass(f), fin, fout);
+            dm += 0.5 * (phx + phn[i]) * link_flux(cc, fclass(f), fin, fout);
         }
     }
     // velocity of the cell at the last step from its post-collision populations
@@ -598,16 +611,22 @@ __device__ __forceinline__ void refill_group(const StepArgs &a, const long long 
     const bool has = active && j >= 1 && j < Q;
     const int ox = has ? k_cx[j] : 0, oy = has ? k_cy[j] : 0, oz = has ? k_cz[j] : 0;
     const int q = has ? nb_local(a.g, c.x, c.y, c.z, ox, oy, oz) : -1;
-    const bool valid = q >= 0 && refill_source(a.flags[cbase + q]);
-    const Cell cq = decode(a.g, cbase + (valid ? q : c.n));
+    // the neighbour's flag and populations are loaded together (the cell's
+    // own at a wall or on an idle lane); values of cells that are not valid
+    // sources are masked out below, never multiplied in
+    const long long qg = cbase + (q >= 0 ? q : c.n);
+    const uint8_t fq = a.flags[qg];
     double d[Q];
-    load_cell<ST>(a, layoutB, cq, d);
+    load_cell<ST>(a, layoutB, decode(a.g, qg), d);
+    issue_fence();
+    const bool valid = q >= 0 && refill_source(fq);
     double r, ux, uy, uz;
     moments_post(d, gr[0], gr[1], gr[2], r, ux, uy, uz);
     const double vw = valid ? 1.0 : 0.0;
     const double nv = group32_sum(vw);
-    const double rs = group32_sum(vw * r);
-    const double usx = group32_sum(vw * ux), usy = group32_sum(vw * uy), usz = group32_sum(vw * uz);
+    const double rs = group32_sum(valid ? r : 0.0);
+    const double usx = group32_sum(valid ? ux : 0.0), usy = group32_sum(valid ? uy : 0.0),
+                 usz = group32_sum(valid ? uz : 0.0);
     double rb = 1.0, ubx = 0.0, uby = 0.0, ubz = 0.0;
     if (nv > 0.0) {
         rb = rs / nv;
@@ -702,7 +721,7 @@ __device__ __forceinline__ void refill_group(const StepArgs &a, const long long 
         double mine = 0.0;
 #pragma unroll
         for (int k = 0; k < Q; ++k) {
-            const double sk = group32_sum(vw * d[k]);
+            const double sk = group32_sum(valid ? d[k] : 0.0);
             if (k == i) mine = sk;
         }
         if (nv > 0.0) out = mine / nv;
@@ -837,6 +856,9 @@ __device__ __forceinline__ void receive(const StepArgs &a, long long gid, double
     const long long cbase = (long long)c.b * a.g.N;
     int nb[Q];
     neighbours(a.g, c, nb);
+    // (the excess-mass work mostly runs inside the bulk kernel, where its
+    // latency is hidden and its register count sets the bulk's occupancy:
+    // these loads are left as dependent as the compiler makes them)
     uint8_t fq[Q];
 #pragma unroll
     for (int i = 1; i < Q; ++i) fq[i] = nb[i] >= 0 ? a.flags[cbase + nb[i]] : uint8_t(0);
