@@ -338,29 +338,33 @@ struct SView {
 };
 
 __device__ __forceinline__ SView slist_view(const SList &L, int32_t *pref) {
-    const int t = threadIdx.x;
+    __shared__ int32_t wave_total[4];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    // both counter loads in flight together
     int v = 0;
-    if (t < L.S) {
-        v = L.cnt[32 * t];
-        v = v < L.seg ? v : L.seg;
+    if (t < L.S) v = L.cnt[32 * t];
+    int o = L.cnt[32 * L.S];
+    v = v < L.seg ? v : L.seg;
+    // inclusive scan: within each wavefront by shuffles, then across the
+    // four wavefronts through shared memory
+    int x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
     }
-    pref[t + 1] = v;
+    if (lane == 63) wave_total[wv] = x;
+    __syncthreads();
+    for (int k = 0; k < wv; ++k) x += wave_total[k];
+    pref[t + 1] = x;
     if (t == 0) pref[0] = 0;
     __syncthreads();
-    // inclusive scan of pref[1..256] (Hillis-Steele)
-    for (int off = 1; off < 256; off <<= 1) {
-        const int add = (t + 1 - off >= 1) ? pref[t + 1 - off] : 0;
-        __syncthreads();
-        pref[t + 1] += add;
-        __syncthreads();
-    }
     SView w;
     w.data = L.data;
     w.pref = pref;
     w.S = L.S;
     w.seg = L.seg;
     w.nseg = pref[L.S];
-    int o = L.cnt[32 * L.S];
     o = o < L.ovf ? o : L.ovf;
     w.total = w.nseg + o;
     return w;
