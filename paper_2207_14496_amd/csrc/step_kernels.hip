@@ -970,7 +970,7 @@ __global__ __launch_bounds__(256) void k_excess(StepArgs a) {
 }
 
 // Workgroups of the last step's excess-mass work ahead of the bulk grid.
-constexpr int EXCESS_WG = 256;
+constexpr int EXCESS_WG = 512;
 
 // The bulk kernel of this step (a) fused with the excess-mass work of the last
 // step (ae).  The two touch disjoint data: the excess work writes mass, fill
