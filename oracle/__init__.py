@@ -48,7 +48,7 @@ class _Params(ctypes.Structure):
                 ("refill", ctypes.c_int), ("omega", ctypes.c_double),
                 ("trt_lambda", ctypes.c_double), ("g", ctypes.c_double * 3),
                 ("sigma", ctypes.c_double), ("p_volume", ctypes.c_double),
-                ("eps_phi", ctypes.c_double)]
+                ("eps_phi", ctypes.c_double), ("smag_cs", ctypes.c_double)]
 
 
 class Counts(ctypes.Structure):
@@ -70,6 +70,8 @@ def lib():
         d, p_ = ctypes.c_double, ctypes.c_void_p
         _lib.orc_feq.argtypes = [d, p_, p_]
         _lib.orc_collide.argtypes = [p_, p_, p_]
+        _lib.orc_cell_omega.argtypes = [p_, p_, p_]
+        _lib.orc_cell_omega.restype = d
         _lib.orc_normal.argtypes = [p_, p_, ctypes.c_long, p_]
         _lib.orc_surface.argtypes = [p_, p_, p_, p_, p_]
         _lib.orc_step.argtypes = [p_, p_, p_, p_, p_, p_, ctypes.c_int, p_]
@@ -99,6 +101,7 @@ class Params:
     sigma: float = 0.0
     p_volume: float = 1.0 / 3.0
     eps_phi: float = 1e-2
+    smag_cs: float = 0.0        # Smagorinsky constant C_S (0 = no turbulence model)
 
     @property
     def N(self) -> int:
@@ -113,6 +116,7 @@ class Params:
         p.collision, p.refill = int(self.collision), int(self.refill)
         p.omega, p.trt_lambda = float(self.omega), float(self.trt_lambda)
         p.sigma, p.p_volume, p.eps_phi = float(self.sigma), float(self.p_volume), float(self.eps_phi)
+        p.smag_cs = float(self.smag_cs)
         return p
 
 
@@ -158,6 +162,15 @@ def collide(params: Params, f, g=None) -> np.ndarray:
     p = params.c()
     lib().orc_collide(ctypes.byref(p), _ptr(gg), _ptr(out))
     return out
+
+
+def cell_omega(params: Params, f, g=None) -> float:
+    """Relaxation rate the collision uses for one cell's post-streaming PDFs
+    (the user-chosen omega, or the Smagorinsky-adjusted one)."""
+    ff = np.ascontiguousarray(f, dtype=np.float64)
+    gg = np.ascontiguousarray(params.g if g is None else g, dtype=np.float64)
+    p = params.c()
+    return float(lib().orc_cell_omega(ctypes.byref(p), _ptr(gg), _ptr(ff)))
 
 
 def normal(params: Params, phi: np.ndarray, n: int) -> np.ndarray:

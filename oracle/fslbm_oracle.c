@@ -55,6 +55,17 @@
  *   R22 TRT: symmetric/antisymmetric split, Lambda = 3/16 by default.
  *   R27 SRT collision relaxes towards equilibrium: Omega = -omega (f - f_eq).
  *   R28 densities used in S6/S7 are sums of the cell's post-collision PDFs.
+ *   R29 Smagorinsky model (Sec. 2.1, turbulence model): tau = tau0 + tau_t
+ *       solves nu_t = c_s^2 tau_t = (C_S dx)^2 S with S = Qbar / (2 rho c_s^2 tau)
+ *       (the total tau, as in the cited Hou et al. model), Qbar = sqrt(2 Q:Q),
+ *       Q_ab = sum_i c_ia c_ib (f_i - f_eq_i) from the post-streaming PDFs and
+ *       the collision's own equilibrium, dx = 1.  Hence
+ *       tau_t = (sqrt(tau0^2 + 2 C_S^2 Qbar / (rho c_s^4)) - tau0) / 2.  The
+ *       printed form puts the bracket after the root (tau_t != 0 at
+ *       equilibrium) and the factor 2 sqrt2, which belongs to the cited
+ *       papers' sqrt(Q:Q) rather than to this Qbar = sqrt(2) sqrt(Q:Q).  With
+ *       TRT the model sets omega+ = 1/tau and omega- follows from Lambda.  The
+ *       GEQ refill keeps the user-chosen tau0.
  */
 #include <math.h>
 #include <stdint.h>
@@ -87,6 +98,7 @@ typedef struct {
     double sigma;      /* surface tension */
     double p_volume;   /* volume (atmospheric) pressure p_V */
     double eps_phi;    /* conversion threshold */
+    double smag_cs;    /* Smagorinsky constant C_S (0 = no turbulence model) */
 } orc_params;
 
 /* Per-step counters that the tests use to check the conversion logic. */
@@ -171,10 +183,35 @@ static void guo_hat(const double u[3], const double F[3], double *Fh)
     }
 }
 
-static double omega_minus(const orc_params *p)
+static double omega_minus_of(double lambda, double omega_plus)
 {
     /* Lambda = (1/omega+ - 1/2)(1/omega- - 1/2) */
-    return 1.0 / (0.5 + p->trt_lambda / (1.0 / p->omega - 0.5));
+    return 1.0 / (0.5 + lambda / (1.0 / omega_plus - 0.5));
+}
+
+/*
+ * Relaxation rate of one cell (R29): the user-chosen omega, or with the
+ * Smagorinsky model 1/tau from the non-equilibrium momentum flux of the
+ * post-streaming PDFs f against the equilibrium feq of density rho.
+ */
+static double cell_omega(const orc_params *p, const double *f, const double *feq, double rho)
+{
+    if (!(p->smag_cs > 0.0)) return p->omega;
+    double Qm[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+    for (int i = 0; i < Q; ++i) {
+        const int c[3] = {CX[i], CY[i], CZ[i]};
+        double ne = f[i] - feq[i];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) Qm[a][b] += c[a] * c[b] * ne;
+    }
+    double qq = 0.0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) qq += Qm[a][b] * Qm[a][b];
+    double qbar = sqrt(2.0 * qq);
+    double tau0 = 1.0 / p->omega;
+    double cs2dx2 = p->smag_cs * p->smag_cs; /* Delta x_LES = 1 */
+    double tau_t = 0.5 * (sqrt(tau0 * tau0 + 2.0 * cs2dx2 * qbar / (rho * CS2 * CS2)) - tau0);
+    return 1.0 / (tau0 + tau_t);
 }
 
 /*
@@ -195,12 +232,13 @@ void orc_collide(const orc_params *p, const double *g, double *f)
     double feq[Q], Fh[Q];
     orc_feq(rho, u, feq);
     guo_hat(u, F, Fh);
+    const double omega = cell_omega(p, f, feq, rho);
     if (p->collision == 0) {
-        double om = p->omega;
+        double om = omega;
         for (int i = 0; i < Q; ++i)
             f[i] = f[i] - om * (f[i] - feq[i]) + (1.0 - om / 2.0) * Fh[i];
     } else {
-        double op_ = p->omega, om_ = omega_minus(p);
+        double op_ = omega, om_ = omega_minus_of(p->trt_lambda, omega);
         double out[Q];
         for (int i = 0; i < Q; ++i) {
             int k = opp(i);
@@ -212,6 +250,21 @@ void orc_collide(const orc_params *p, const double *g, double *f)
         }
         for (int i = 0; i < Q; ++i) f[i] = out[i];
     }
+}
+
+/* The relaxation rate orc_collide would use for these post-streaming PDFs. */
+double orc_cell_omega(const orc_params *p, const double *g, const double *f)
+{
+    double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < Q; ++i) {
+        rho += f[i];
+        j[0] += CX[i] * f[i]; j[1] += CY[i] * f[i]; j[2] += CZ[i] * f[i];
+    }
+    double u[3];
+    for (int a = 0; a < 3; ++a) u[a] = rho * g[a] / (2.0 * rho) + j[a] / rho;
+    double feq[Q];
+    orc_feq(rho, u, feq);
+    return cell_omega(p, f, feq, rho);
 }
 
 /* rho and u of a cell from its stored post-collision PDFs (R3). */
