@@ -115,6 +115,15 @@ typedef struct fslbm_params {
     const double *omega_b;  /* optional HOST array [B]: per-domain omega, or NULL   */
     const double *gravity_b;/* optional HOST array [B][3]: per-domain g, or NULL    */
     void *stream;           /* hipStream_t for all work                             */
+    double smagorinsky_cs;  /* Smagorinsky constant C_S of the turbulence model
+                             * (Sec. 2.1, turbulence model), >= 0; 0 disables it.
+                             * Per cell tau = (tau0 + sqrt(tau0^2 + 2 C_S^2 Qbar /
+                             * (rho c_s^4))) / 2 with tau0 = 1/omega, Qbar =
+                             * sqrt(2 Q:Q), Q_ab = sum_i c_ia c_ib (f_i - f_eq_i)
+                             * of the post-streaming populations, dx = 1 (the
+                             * solution of nu_t = c_s^2 (tau - tau0) = C_S^2 Qbar /
+                             * (2 rho c_s^2 tau)).  With TRT it sets omega+ = 1/tau
+                             * and omega- follows from trt_lambda.                 */
 } fslbm_params;
 
 typedef struct fslbm_ctx fslbm_ctx;

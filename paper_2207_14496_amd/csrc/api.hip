@@ -77,6 +77,7 @@ const char *validate(const fslbm_params *p) {
     if (p->refill < FSLBM_REFILL_EQ || p->refill > FSLBM_REFILL_AVG) return "unknown refill scheme";
     if (p->collision == FSLBM_TRT && !(p->trt_lambda > 0.0)) return "trt_lambda must be > 0";
     if (!(p->eps_phi >= 0.0)) return "eps_phi must be >= 0";
+    if (!(p->smagorinsky_cs >= 0.0) || !(p->smagorinsky_cs < 1e3)) return "smagorinsky_cs must be finite and >= 0";
     if (p->omega_b)
         for (int b = 0; b < p->batch; ++b)
             if (!(p->omega_b[b] > 0.0 && p->omega_b[b] < 2.0)) return "omega_b must lie in (0, 2)";
@@ -359,6 +360,8 @@ StepArgs make_args(fslbm_ctx *c, int parity) {
     a.omega = at<double>(c, c->L.omega);
     a.grav = at<double>(c, c->L.grav);
     a.trt_lambda = p.trt_lambda;
+    // 2 C_S^2 / c_s^4 with c_s^2 = 1/3
+    a.les_k = p.smagorinsky_cs > 0.0 ? 18.0 * p.smagorinsky_cs * p.smagorinsky_cs : 0.0;
     a.sigma = p.sigma;
     a.p_volume = p.p_volume;
     a.eps_phi = p.eps_phi;

@@ -224,6 +224,7 @@ struct StepArgs {
     const double *omega;   // [B]
     const double *grav;    // [B][3]
     double trt_lambda;
+    double les_k;          // Smagorinsky: 2 C_S^2 / c_s^4 (0 = no turbulence model)
     double sigma, p_volume, eps_phi;
     SList list_if;          // interface cells of this step, built by the bulk kernel in tile order
     SList list_if_prev;     // the same list of the last step

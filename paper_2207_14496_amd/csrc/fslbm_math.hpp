@@ -26,8 +26,14 @@ __device__ __forceinline__ T guo_hat(int i, T ux, T uy, T uz, T Fx, T Fy, T Fz) 
 // Collision of one cell in place on shifted populations (Sec. 2.1): rho and the
 // half-force-shifted velocity, F = rho g, SRT (relaxation towards equilibrium)
 // or TRT (symmetric/antisymmetric split with rates om and omm).
+// COLL: bit 0 selects TRT (else SRT), bit 1 the Smagorinsky turbulence model
+// (Sec. 2.1): the relaxation time tau0 = 1/om becomes
+// tau = (tau0 + sqrt(tau0^2 + les_k Qbar / rho)) / 2, les_k = 2 C_S^2 / c_s^4,
+// Qbar = sqrt(2 Q:Q) of the non-equilibrium momentum flux of the incoming
+// populations; with TRT om- then follows from lambda.
 template <typename T, int COLL>
-__device__ __forceinline__ void collide(T (&d)[Q], T om, T omm, T gx, T gy, T gz) {
+__device__ __forceinline__ void collide(T (&d)[Q], T om, T omm, T gx, T gy, T gz, T les_k = T(0),
+                                        T lambda = T(0)) {
     T drho = T(0), jx = T(0), jy = T(0), jz = T(0);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -41,7 +47,27 @@ __device__ __forceinline__ void collide(T (&d)[Q], T om, T omm, T gx, T gy, T gz
     T ir = T(1) / rho;
     T ux = (jx + T(0.5) * Fx) * ir, uy = (jy + T(0.5) * Fy) * ir, uz = (jz + T(0.5) * Fz) * ir;
     T uu = ux * ux + uy * uy + uz * uz;
-    if (COLL == 0) {
+    if (COLL & 2) {
+        // momentum flux of the non-equilibrium part (the shift w_i cancels)
+        T qxx = T(0), qyy = T(0), qzz = T(0), qxy = T(0), qxz = T(0), qyz = T(0);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const T ne = d[i] - feq_shift<T>(i, rho, drho, ux, uy, uz, uu);
+            if (cx(i)) qxx += ne;
+            if (cy(i)) qyy += ne;
+            if (cz(i)) qzz += ne;
+            if (cx(i) * cy(i)) qxy += T(cx(i) * cy(i)) * ne;
+            if (cx(i) * cz(i)) qxz += T(cx(i) * cz(i)) * ne;
+            if (cy(i) * cz(i)) qyz += T(cy(i) * cz(i)) * ne;
+        }
+        const T qq = qxx * qxx + qyy * qyy + qzz * qzz + T(2) * (qxy * qxy + qxz * qxz + qyz * qyz);
+        const T qbar = sqrt(T(2) * qq);
+        const T tau0 = T(1) / om;
+        const T tau = T(0.5) * (tau0 + sqrt(tau0 * tau0 + les_k * qbar * ir));
+        om = T(1) / tau;
+        if (COLL & 1) omm = T(1) / (T(0.5) + lambda / (tau - T(0.5)));
+    }
+    if ((COLL & 1) == 0) {
         T pf = T(1) - T(0.5) * om;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {

@@ -25,6 +25,8 @@
 // list kernels, so work that can share a kernel does.  Inside the list
 // kernels every load that does not depend on another is issued first, with
 // clamped in-bounds addresses for walls, and only then selected.
+#include <type_traits>
+
 #include "fslbm_kernels.hpp"
 #include "fslbm_math.hpp"
 
@@ -402,11 +404,11 @@ __device__ __forceinline__ bool update_cell(const StepArgs &a, const long long g
     const double *gr = a.grav + 3 * c.b;
     const T om = T(a.omega[c.b]);
     T omm = om;
-    if (COLL == 1) {
+    if (COLL & 1) {
         double op = a.omega[c.b];
         omm = T(1.0 / (0.5 + a.trt_lambda / (1.0 / op - 0.5)));
     }
-    collide<T, COLL>(d, om, omm, T(gr[0]), T(gr[1]), T(gr[2]));
+    collide<T, COLL>(d, om, omm, T(gr[0]), T(gr[1]), T(gr[2]), T(a.les_k), T(a.trt_lambda));
 
     C::store(base + n, d[0]);
 #pragma unroll
@@ -1010,6 +1012,23 @@ static void launch_bulk_t(const StepArgs &a, const StepArgs *pending, hipStream_
         launch_bulk(k_stream_collide<ST, COLL, PAR>, a, s);
 }
 
+// Calls f(C, P) with the collision variant and the step parity as
+// compile-time constants (std::integral_constant).
+template <int ST, typename F>
+static void launch_coll(int coll, int parity, F &&f) {
+    using std::integral_constant;
+    switch (coll * 2 + parity) {
+        case 0: f(integral_constant<int, 0>{}, integral_constant<int, 0>{}); break;
+        case 1: f(integral_constant<int, 0>{}, integral_constant<int, 1>{}); break;
+        case 2: f(integral_constant<int, 1>{}, integral_constant<int, 0>{}); break;
+        case 3: f(integral_constant<int, 1>{}, integral_constant<int, 1>{}); break;
+        case 4: f(integral_constant<int, 2>{}, integral_constant<int, 0>{}); break;
+        case 5: f(integral_constant<int, 2>{}, integral_constant<int, 1>{}); break;
+        case 6: f(integral_constant<int, 3>{}, integral_constant<int, 0>{}); break;
+        default: f(integral_constant<int, 3>{}, integral_constant<int, 1>{}); break;
+    }
+}
+
 template <int ST>
 static void launch_step_t(const StepArgs &a, int collision, int scheme, hipStream_t s,
                           const BulkEvents *ev, const StepArgs *pending, bool finish) {
@@ -1024,21 +1043,16 @@ static void launch_step_t(const StepArgs &a, int collision, int scheme, hipStrea
         hipLaunchKernelGGL(k_curvature, dim3(lb), dim3(256), 0, s, a);
     }
     if (ev) (void)hipEventRecord(ev->before, s);
-    if (collision == 0) {
-        if (a.parity == 0) launch_bulk_t<ST, 0, 0>(a, pending, s);
-        else launch_bulk_t<ST, 0, 1>(a, pending, s);
-    } else {
-        if (a.parity == 0) launch_bulk_t<ST, 1, 0>(a, pending, s);
-        else launch_bulk_t<ST, 1, 1>(a, pending, s);
-    }
+    // collision variant: bit 0 TRT, bit 1 Smagorinsky turbulence model
+    const int coll = (collision ? 1 : 0) | (a.les_k > 0.0 ? 2 : 0);
+    launch_coll<ST>(coll, a.parity, [&](auto C, auto P) {
+        launch_bulk_t<ST, decltype(C)::value, decltype(P)::value>(a, pending, s);
+    });
     if (ev) (void)hipEventRecord(ev->after, s);
-    if (collision == 0) {
-        if (a.parity == 0) hipLaunchKernelGGL((k_interface<ST, 0, 0>), dim3(lb), dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((k_interface<ST, 0, 1>), dim3(lb), dim3(256), 0, s, a);
-    } else {
-        if (a.parity == 0) hipLaunchKernelGGL((k_interface<ST, 1, 0>), dim3(lb), dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((k_interface<ST, 1, 1>), dim3(lb), dim3(256), 0, s, a);
-    }
+    launch_coll<ST>(coll, a.parity, [&](auto C, auto P) {
+        hipLaunchKernelGGL((k_interface<ST, decltype(C)::value, decltype(P)::value>), dim3(lb), dim3(256), 0,
+                           s, a);
+    });
     hipLaunchKernelGGL(k_resolve, dim3(lb), dim3(256), 0, s, a);
     switch (scheme) {
         case 0: hipLaunchKernelGGL((k_convert<ST, 0>), dim3(lb), dim3(256), 0, s, a); break;

@@ -48,7 +48,8 @@ class CParams(ctypes.Structure):
                 ("trt_lambda", ctypes.c_double), ("gravity", ctypes.c_double * 3),
                 ("sigma", ctypes.c_double), ("p_volume", ctypes.c_double),
                 ("eps_phi", ctypes.c_double), ("omega_b", ctypes.POINTER(ctypes.c_double)),
-                ("gravity_b", ctypes.POINTER(ctypes.c_double)), ("stream", ctypes.c_void_p)]
+                ("gravity_b", ctypes.POINTER(ctypes.c_double)), ("stream", ctypes.c_void_p),
+                ("smagorinsky_cs", ctypes.c_double)]
 
 
 class CDiag(ctypes.Structure):
@@ -128,6 +129,7 @@ class Params:
     eps_phi: float = 1e-2
     omega_b: tuple | None = None      # per-domain omega [B]
     gravity_b: tuple | None = None    # per-domain gravity [B][3]
+    smagorinsky_cs: float = 0.0       # Smagorinsky constant (0 = no turbulence model)
 
     @property
     def N(self) -> int:
@@ -142,6 +144,7 @@ class Params:
         p.collision, p.storage, p.refill = int(self.collision), int(self.storage), int(self.refill)
         p.omega, p.trt_lambda = float(self.omega), float(self.trt_lambda)
         p.sigma, p.p_volume, p.eps_phi = float(self.sigma), float(self.p_volume), float(self.eps_phi)
+        p.smagorinsky_cs = float(self.smagorinsky_cs)
         keep = []
         if self.omega_b is not None:
             arr = (ctypes.c_double * self.batch)(*[float(v) for v in self.omega_b])

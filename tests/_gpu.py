@@ -13,7 +13,8 @@ LIQ, IFC, GAS = 1, 2, 4
 
 def params_from_oracle(p: oracle.Params, storage=fslbm.F64, batch=1, **kw) -> fslbm.Params:
     q = fslbm.Params(p.nx, p.ny, p.nz, batch, tuple(p.periodic), p.collision, storage, p.refill,
-                     p.omega, p.trt_lambda, tuple(p.g), p.sigma, p.p_volume, p.eps_phi)
+                     p.omega, p.trt_lambda, tuple(p.g), p.sigma, p.p_volume, p.eps_phi,
+                     smagorinsky_cs=p.smag_cs)
     for k, v in kw.items():
         setattr(q, k, v)
     return q

@@ -97,6 +97,34 @@ def test_dam_break_small_step_by_step():
     sim.close()
 
 
+@pytest.mark.parametrize("collision", [0, 1])
+def test_smagorinsky_random_states(collision):
+    """Turbulence model on (Sec. 2.1): random interface states, three steps,
+    SRT and TRT."""
+    for seed in (20 + collision, 30 + collision):
+        s = setups.random_interface_state(12, 10, 9, seed, periodic=(1, 1, 1), g=(0.0, 0.0, -1e-4),
+                                          collision=collision)
+        p = oracle_params(s, smag_cs=0.15)
+        st = oracle_state(s, p)
+        announce(f"Smagorinsky random state seed {seed} collision {collision}")
+        _run_pair(p, st, 3, f"Smagorinsky seed {seed}")
+
+
+def test_smagorinsky_dam_break_multi_step_calls():
+    """Turbulence model on: the small dam break (TRT, walls), eight steps per
+    call, against the oracle every call."""
+    s = setups.rect_dam_break(40, 6, 24, width=12, height=16, g=2e-4, refill=0, omega=1.99)
+    p = oracle_params(s, smag_cs=0.1)
+    st = oracle_state(s, p)
+    announce("Smagorinsky dam break 40x6x24")
+    sim = sim_from_states(p, [st])
+    for k in range(5):
+        sim.step(8)
+        oracle.step(p, st, 8)
+        compare(fields_np(sim), 0, st, 1e-11, 1e-11, 1e-11, what=f"LES dam break step {8 * (k + 1)}")
+    sim.close()
+
+
 def test_surface_tension_drop():
     """Curvature path: a small 3-D drop with surface tension (sigma != 0)."""
     n = 20
