@@ -26,6 +26,8 @@ gravity_wave_schemes  (--gravity-wave-schemes) the same wave at L = 800 (FP64)
            with each refilling scheme, next to the per-scheme series the paper prints.
 dam_break  rectangular dam break 256 x 128 x 64 (FP32), each refilling scheme,
            20000 steps: front position, residual height, stability, mass drift.
+dam_break_les  the same at the paper's omega = 1.9995 with its Smagorinsky
+           turbulence model (C_S = 0.1).
 drop_impact  drop impact 256^3 with surface tension, every storage type, 8000
            steps: centre-column height, cavity depth, mass drift, and the
            fill-level / flag differences against the FP64 run.
@@ -219,6 +221,9 @@ def main():
         result["gravity_wave_schemes"] = gravity_wave_schemes(fslbm)
     if not args.no_reports:
         result["dam_break"] = dam_break_report(fslbm, setups, torch, args.dam_break_steps)
+        # the paper's dam-break relaxation rate, runnable with its turbulence model
+        result["dam_break_les"] = dam_break_report(fslbm, setups, torch, args.dam_break_steps,
+                                                   omega=1.9995, smagorinsky_cs=0.1)
         result["drop_impact"] = drop_impact_report(fslbm, setups, torch, args.drop_steps)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
@@ -274,18 +279,19 @@ def gravity_wave_schemes(fslbm, L=800, t_star_end=15.0):
     return out
 
 
-def dam_break_report(fslbm, setups, torch, steps, every=1000):
+def dam_break_report(fslbm, setups, torch, steps, every=1000, omega=1.95, smagorinsky_cs=0.0):
     """Rectangular dam break 256x128x64 (FP32 storage), each refilling scheme:
     front position and residual height every `every` steps in cells and in the
     paper's dimensionless form (w* = front / W, h* = height / H, t* = t sqrt(2 g / W),
-    Sec. 4.2), the first check at which the run was unstable, and the mass drift."""
+    Sec. 4.2), the first check at which the run was unstable, and the mass drift.
+    omega / smagorinsky_cs: the relaxation rate and the turbulence model."""
     import math
     from paper_2207_14496_amd import observe
     out = []
     for scheme, name in enumerate(("EQ", "EQ+NEQ", "GEQ", "EXT", "AVG")):
-        s = setups.rect_dam_break(refill=scheme)
+        s = setups.rect_dam_break(refill=scheme, omega=omega)
         W, H, g = s.meta["width"], s.meta["height"], abs(s.g[2])
-        sim = fslbm.from_setup(s, storage=fslbm.F32)
+        sim = fslbm.from_setup(s, storage=fslbm.F32, smagorinsky_cs=smagorinsky_cs)
         m0 = sim.diagnostics()[0]["total_mass"]
         series, unstable_at, done, t0 = [], None, 0, time.perf_counter()
         while done < steps:
@@ -311,8 +317,10 @@ def dam_break_report(fslbm, setups, torch, steps, every=1000):
         torch.cuda.empty_cache()
         out.append(rec)
         last = series[-1] if series else None
-        log(f"  dam break {name}: {done} steps, unstable at {unstable_at}, last {last}")
-    return {"workload": "rect-dam-break 256x128x64 D3Q19 TRT omega=1.95 g=2e-5, f32 shifted PDFs",
+        log(f"  dam break {name} (omega {omega}, C_S {smagorinsky_cs}): {done} steps, "
+            f"unstable at {unstable_at}, last {last}")
+    return {"workload": f"rect-dam-break 256x128x64 D3Q19 TRT omega={omega} g=2e-5, f32 shifted PDFs"
+                        + (f", Smagorinsky C_S={smagorinsky_cs}" if smagorinsky_cs else ""),
             "schemes": out}
 
 
