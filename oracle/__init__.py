@@ -48,7 +48,8 @@ class _Params(ctypes.Structure):
                 ("refill", ctypes.c_int), ("omega", ctypes.c_double),
                 ("trt_lambda", ctypes.c_double), ("g", ctypes.c_double * 3),
                 ("sigma", ctypes.c_double), ("p_volume", ctypes.c_double),
-                ("eps_phi", ctypes.c_double), ("smag_cs", ctypes.c_double)]
+                ("eps_phi", ctypes.c_double), ("smag_cs", ctypes.c_double),
+                ("free_slip", ctypes.c_int)]
 
 
 class Counts(ctypes.Structure):
@@ -102,6 +103,7 @@ class Params:
     p_volume: float = 1.0 / 3.0
     eps_phi: float = 1e-2
     smag_cs: float = 0.0        # Smagorinsky constant C_S (0 = no turbulence model)
+    free_slip: int = 0          # walls: 0 no-slip (bounce-back), 1 free-slip (specular)
 
     @property
     def N(self) -> int:
@@ -117,6 +119,7 @@ class Params:
         p.omega, p.trt_lambda = float(self.omega), float(self.trt_lambda)
         p.sigma, p.p_volume, p.eps_phi = float(self.sigma), float(self.p_volume), float(self.eps_phi)
         p.smag_cs = float(self.smag_cs)
+        p.free_slip = int(self.free_slip)
         return p
 
 

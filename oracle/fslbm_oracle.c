@@ -66,6 +66,14 @@
  *       papers' sqrt(Q:Q) rather than to this Qbar = sqrt(2) sqrt(Q:Q).  With
  *       TRT the model sets omega+ = 1/tau and omega- follows from Lambda.  The
  *       GEQ refill keeps the user-chosen tau0.
+ *   R30 free-slip walls (Sec. 2.1): a population whose next cell lies in a
+ *       wall comes back with the wall-normal components of its velocity
+ *       reversed, in the cell shifted by the remaining (tangential)
+ *       components; so the pair (n, i) is linked to that cell for streaming
+ *       and for the mass exchange (mass stays conserved), and a gas cell
+ *       there is rebuilt by anti-bounce-back like any gas source.  Classes,
+ *       conflicts, refill sources, excess receivers and normals keep treating
+ *       walls as no cells.
  */
 #include <math.h>
 #include <stdint.h>
@@ -99,6 +107,7 @@ typedef struct {
     double p_volume;   /* volume (atmospheric) pressure p_V */
     double eps_phi;    /* conversion threshold */
     double smag_cs;    /* Smagorinsky constant C_S (0 = no turbulence model) */
+    int free_slip;     /* walls: 0 no-slip (bounce-back), 1 free-slip (specular) */
 } orc_params;
 
 /* Per-step counters that the tests use to check the conversion logic. */
@@ -127,6 +136,42 @@ static long nbr(const orc_params *p, long n, int dx, int dy, int dz)
     if (y < 0 || y >= ny) { if (!p->periodic[1]) return -1; y = (y + ny) % ny; }
     if (z < 0 || z >= nz) { if (!p->periodic[2]) return -1; z = (z + nz) % nz; }
     return (z * ny + y) * nx + x;
+}
+
+/* Direction whose velocity is c with the components in mask negated. */
+static int dir_of(int x, int y, int z)
+{
+    for (int k = 0; k < Q; ++k)
+        if (CX[k] == x && CY[k] == y && CZ[k] == z) return k;
+    return -1;
+}
+
+/*
+ * Where a population leaving cell n along c_i goes next (R30): the cell at
+ * n + c_i with direction i, or, when that lies in a wall, with free-slip walls
+ * the cell n + c_i with the wall-crossing components left out and direction j
+ * (those components of c_i reversed); with no-slip walls n itself, opp(i).
+ * Returns 1 if a wall was hit.
+ */
+static int next_link(const orc_params *p, long n, int i, long *m, int *j)
+{
+    long nx = p->nx, ny = p->ny, nz = p->nz;
+    long pos[3] = {n % nx, (n / nx) % ny, n / (nx * ny)};
+    const long len[3] = {nx, ny, nz};
+    int c[3] = {CX[i], CY[i], CZ[i]};
+    int hit = 0;
+    for (int a = 0; a < 3; ++a) {
+        long q = pos[a] + c[a];
+        if (q >= 0 && q < len[a]) { pos[a] = q; continue; }
+        if (p->periodic[a]) { pos[a] = (q + len[a]) % len[a]; continue; }
+        hit = 1;
+        c[a] = -c[a];              /* reflected; the position stays in this layer */
+    }
+    if (!hit) { *m = (pos[2] * ny + pos[1]) * nx + pos[0]; *j = i; return 0; }
+    if (!p->free_slip) { *m = n; *j = opp(i); return 1; }
+    *m = (pos[2] * ny + pos[1]) * nx + pos[0];
+    *j = dir_of(c[0], c[1], c[2]);
+    return 1;
 }
 
 /* D3Q19 neighbour table of the current domain: entry i*N+n is the cell at
@@ -520,6 +565,7 @@ static void stream_cell(const orc_params *p, const uint8_t *flag, const double *
     int need_u = 0;
     for (int i = 1; i < Q; ++i) {
         long s = nb19(p, n, opp(i));
+        if (s < 0 && p->free_slip) { int jj; next_link(p, n, opp(i), &s, &jj); }
         if (s >= 0 && flag[s] == GAS) need_u = 1;
     }
     if (need_u) moments_post(p, fs, N, n, &rS, uS);
@@ -527,12 +573,19 @@ static void stream_cell(const orc_params *p, const uint8_t *flag, const double *
     for (int i = 1; i < Q; ++i) {
         long s = nb19(p, n, opp(i));
         int io = opp(i);
+        int k = i;                    /* direction in which the source sent it */
+        if (s < 0 && p->free_slip) {
+            /* specular wall (R30): the source is where opp(i) from n leads */
+            int jj;
+            next_link(p, n, io, &s, &jj);
+            k = opp(jj);
+        }
         if (s < 0) {
             fn[i] = fs[(long)io * N + n];                         /* bounce-back */
         } else if (flag[s] == GAS) {                               /* anti-bounce-back */
             fn[i] = feq_i(i, rhoG[n], uS) + feq_i(io, rhoG[n], uS) - fs[(long)io * N + n];
         } else {
-            fn[i] = fs[(long)i * N + s];                           /* streaming */
+            fn[i] = fs[(long)k * N + s];                           /* streaming */
         }
     }
 }
@@ -580,8 +633,14 @@ static int step_once(const orc_params *p, uint8_t *flag, double *f, double *m, d
             double dm = 0.0;
             for (int i = 1; i < Q; ++i) {
                 long k = nb19(p, n, i);
+                int kin = opp(i);     /* direction of the population k sends to n */
+                if (k < 0 && p->free_slip) {
+                    int jj;
+                    if (next_link(p, n, i, &k, &jj) && k == n) continue;   /* returns to n itself */
+                    kin = opp(jj);
+                }
                 if (k < 0 || flag[k] == GAS) continue;
-                double fin = fs[(long)opp(i) * N + k];
+                double fin = fs[(long)kin * N + k];
                 double fout = fs[(long)i * N + n];
                 if (flag[k] == LIQ) dm += fin - fout;
                 else dm += 0.5 * (phis[n] + phis[k]) * link_flux(cls[n], cls[k], fin, fout);
