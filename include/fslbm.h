@@ -124,6 +124,12 @@ typedef struct fslbm_params {
                              * solution of nu_t = c_s^2 (tau - tau0) = C_S^2 Qbar /
                              * (2 rho c_s^2 tau)).  With TRT it sets omega+ = 1/tau
                              * and omega- follows from trt_lambda.                 */
+    int32_t free_slip;      /* walls (Sec. 2.1): 0 no-slip (half-way bounce-back),
+                             * 1 free-slip (specular: a population that would
+                             * enter a wall comes back with its wall-normal
+                             * velocity components reversed, in the cell shifted
+                             * by the other components; the mass exchange follows
+                             * the same path)                                        */
 } fslbm_params;
 
 typedef struct fslbm_ctx fslbm_ctx;

@@ -40,6 +40,7 @@ const char *check_config(const fslbm_ctx *c) {
     if (p.collision != FSLBM_SRT) return "the adjoint needs SRT collision";
     if (p.sigma != 0.0) return "the adjoint needs sigma = 0";
     if (p.smagorinsky_cs != 0.0) return "the adjoint needs smagorinsky_cs = 0";
+    if (p.free_slip != 0) return "the adjoint needs no-slip walls";
     if (p.refill != FSLBM_REFILL_EQ) return "the adjoint needs EQ refilling";
     if (p.batch > 65535) return "the adjoint supports at most 65535 domains";
     return nullptr;

@@ -78,6 +78,7 @@ const char *validate(const fslbm_params *p) {
     if (p->collision == FSLBM_TRT && !(p->trt_lambda > 0.0)) return "trt_lambda must be > 0";
     if (!(p->eps_phi >= 0.0)) return "eps_phi must be >= 0";
     if (!(p->smagorinsky_cs >= 0.0) || !(p->smagorinsky_cs < 1e3)) return "smagorinsky_cs must be finite and >= 0";
+    if (p->free_slip != 0 && p->free_slip != 1) return "free_slip must be 0 or 1";
     if (p->omega_b)
         for (int b = 0; b < p->batch; ++b)
             if (!(p->omega_b[b] > 0.0 && p->omega_b[b] < 2.0)) return "omega_b must lie in (0, 2)";
@@ -339,6 +340,7 @@ StepArgs make_args(fslbm_ctx *c, int parity) {
     const fslbm_params &p = c->p;
     a.g.nx = p.nx; a.g.ny = p.ny; a.g.nz = p.nz;
     for (int k = 0; k < 3; ++k) a.g.per[k] = p.periodic[k];
+    a.g.slip = p.free_slip;
     a.g.N = (long long)p.nx * p.ny * p.nz;
     a.g.BN = a.g.N * p.batch;
     a.g.dx = FastDiv::make(uint32_t(p.nx));

@@ -110,6 +110,7 @@ struct FastDiv {
 struct Geom {
     int nx, ny, nz;
     int per[3];
+    int slip;         // walls: 0 no-slip (bounce-back), 1 free-slip (specular)
     long long N;      // cells per domain
     long long BN;     // cells in all domains (< 2^31)
     FastDiv dx, dy, dN;
@@ -129,6 +130,28 @@ struct Cell {
     int b, x, y, z;
     int n;        // domain-local index
 };
+
+// Where a population leaving cell (x,y,z) along (ox,oy,oz) goes next when
+// that cell lies in a wall and the walls are free-slip (Sec. 2.1, specular
+// reflection): the wall-crossing components are reversed and the population
+// arrives in the cell shifted by the others.  Returns the domain-local cell;
+// (rx,ry,rz) receives the arrival direction.  Only called for a move that hits
+// a wall.
+__device__ __forceinline__ int slip_target(const Geom &g, int x, int y, int z, int ox, int oy, int oz,
+                                           int &rx, int &ry, int &rz) {
+    auto axis = [](int p, int o, int n, int per, int &r) -> int {
+        int q = p + o;
+        r = o;
+        if (q >= 0 && q < n) return q;
+        if (per) return q < 0 ? q + n : q - n;
+        r = -o;   // reflected: stays in this layer
+        return p;
+    };
+    const int X = axis(x, ox, g.nx, g.per[0], rx);
+    const int Y = axis(y, oy, g.ny, g.per[1], ry);
+    const int Z = axis(z, oz, g.nz, g.per[2], rz);
+    return (Z * g.ny + Y) * g.nx + X;
+}
 
 __device__ __forceinline__ Cell decode(const Geom &g, long long gid) {
     Cell c;
@@ -154,8 +177,10 @@ __device__ __forceinline__ long long nb_dir(const Geom &g, const Cell &c, int i)
 // ------------------------------------------------------------------ AA slots
 // In-place streaming (AA pattern, Bailey et al. 2009).  After an even number of
 // steps ("layout A") f*_i(x) sits in slot (opp(i), x).  After an odd number
-// ("layout B") it sits in slot (i, x + c_i), or in (opp(i), x) when x + c_i is
-// a wall.  Slot (d, n) of domain b is pdf[(b*19 + d)*N + n].
+// ("layout B") it sits in slot (i, x + c_i), or, when x + c_i is a wall, in
+// (opp(i), x) with no-slip walls and in (j, m) with free-slip walls, m and j
+// being the cell and direction of its specular reflection (slip_target).
+// Slot (d, n) of domain b is pdf[(b*19 + d)*N + n].
 
 // The lattice again as tables, for the few places that index a direction with
 // a runtime value (one lane per direction).
@@ -163,24 +188,49 @@ __device__ __constant__ const int8_t k_cx[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, 
 __device__ __constant__ const int8_t k_cy[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
 __device__ __constant__ const int8_t k_cz[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
 
-// Flat index of the slot holding f*_i of cell c in the given layout, for a
-// runtime direction i.
+// Direction index of lattice velocity (x, y, z) (a D3Q19 velocity).
+__device__ __forceinline__ int dir_index(int x, int y, int z) {
+    int k = 0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) k = (cx(i) == x && cy(i) == y && cz(i) == z) ? i : k;
+    return k;
+}
+
+// Flat index of the slot holding f*_i of cell c in the given layout (after
+// an odd number of steps a population that went into a free-slip wall sits
+// in its reflected arrival slot), for a runtime direction i.
+__device__ __forceinline__ int dir_index(int x, int y, int z);
+
+// SLIP: 1 free-slip walls, 0 no-slip walls, -1 as the geometry says (the
+// kernels that run every step fix it at compile time).
+template <int SLIP = -1>
 __device__ __forceinline__ long long slot_flat_rt(const Geom &g, int layoutB, const Cell &c, int i) {
     const long long base = (long long)c.b * Q * g.N;
     if (layoutB && i > 0) {
         int k = nb_local(g, c.x, c.y, c.z, k_cx[i], k_cy[i], k_cz[i]);
         if (k >= 0) return base + (long long)i * g.N + k;
+        if (SLIP == 1 || (SLIP < 0 && g.slip)) {
+            int rx, ry, rz;
+            const int m = slip_target(g, c.x, c.y, c.z, k_cx[i], k_cy[i], k_cz[i], rx, ry, rz);
+            return base + (long long)dir_index(rx, ry, rz) * g.N + m;
+        }
     }
     const int o = i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1);
     return base + (long long)o * g.N + c.n;
 }
 
 // Flat index of the slot holding f*_i of cell c in the given layout.
+template <int SLIP = -1>
 __device__ __forceinline__ long long slot_flat(const Geom &g, int layoutB, const Cell &c, int i) {
     const long long base = (long long)c.b * Q * g.N;
     if (layoutB) {
         int k = nb_local(g, c.x, c.y, c.z, cx(i), cy(i), cz(i));
         if (k >= 0) return base + (long long)i * g.N + k;
+        if (i > 0 && (SLIP == 1 || (SLIP < 0 && g.slip))) {
+            int rx, ry, rz;
+            const int m = slip_target(g, c.x, c.y, c.z, cx(i), cy(i), cz(i), rx, ry, rz);
+            return base + (long long)dir_index(rx, ry, rz) * g.N + m;
+        }
     }
     return base + (long long)opp(i) * g.N + c.n;
 }

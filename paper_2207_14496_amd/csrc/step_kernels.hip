@@ -79,12 +79,13 @@ __device__ __forceinline__ void store_fo(const StepArgs &a, int i, long long gid
     C::store(static_cast<typename C::M *>(a.fo) + fo_index(gid, i), typename C::T(v));
 }
 
-// Shifted post-collision populations of a cell in the given layout.
-template <int ST>
+// Shifted post-collision populations of a cell in the given layout (SLIP as
+// for slot_flat).
+template <int ST, int SLIP = -1>
 __device__ __forceinline__ void load_cell(const StepArgs &a, int layoutB, const Cell &c,
                                           double (&d)[Q]) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) d[i] = load_slot<ST>(a, slot_flat(a.g, layoutB, c, i));
+    for (int i = 0; i < Q; ++i) d[i] = load_slot<ST>(a, slot_flat<SLIP>(a.g, layoutB, c, i));
 }
 
 __device__ __forceinline__ int fclass(uint8_t fl) {
@@ -269,7 +270,7 @@ __global__ __launch_bounds__(256) void k_curvature(StepArgs a) {
 // reconstruction) and the cell's own outgoing populations of the last step
 // (fo buffer); anti-bounce-back for populations arriving from gas, with the
 // cell's velocity of the last step; phi = m/rho; conversion marks.
-template <int ST, int PAR>
+template <int ST, int PAR, bool SLIP>
 __device__ __forceinline__ bool interface_part(const StepArgs &a, const long long gid, const uint8_t fl,
                                                const Cell &c, const int (&src)[Q],
                                                typename Codec<ST>::T (&d)[Q]) {
@@ -304,7 +305,8 @@ __device__ __forceinline__ bool interface_part(const StepArgs &a, const long lon
     for (int i = 1; i < Q; ++i) {
         const int o = opp(i);
         const uint8_t f = fn[o];
-        if (src[o] < 0 || (f & F_GAS)) continue;
+        // (no wall link; a free-slip path back into this cell exchanges nothing)
+        if (src[o] < 0 || (SLIP && src[o] == c.n) || (f & F_GAS)) continue;
         const double w = wgt<double>(i);
         const double fin = w + double(d[o]);    // f*_opp(i)(x + c_i, t)
         const double fout = w + double(fo[i]);  // f*_i(x, t)
@@ -380,18 +382,32 @@ __device__ __forceinline__ bool update_cell(const StepArgs &a, const long long g
         if (X < 0 || Y < 0 || Z < 0) return -1;
         return (Z * g.ny + Y) * g.nx + X;
     };
-    int src[Q];   // source cell x - c_i of each incoming population (-1 = wall)
+    constexpr bool SLIPC = (COLL & 4) != 0;   // free-slip walls
+    // source cell x - c_i of each incoming population (-1 = no-slip wall) and
+    // the direction it was sent in (i, or at a free-slip wall the reflected
+    // direction from the cell the specular path comes from)
+    int src[Q], sdir[Q];
     src[0] = n;
+    sdir[0] = 0;
 #pragma unroll
-    for (int i = 1; i < Q; ++i) src[i] = nbl(-cx(i), -cy(i), -cz(i));
+    for (int i = 1; i < Q; ++i) {
+        src[i] = nbl(-cx(i), -cy(i), -cz(i));
+        sdir[i] = i;
+        if (SLIPC && src[i] < 0) {
+            int rx, ry, rz;
+            src[i] = slip_target(g, c.x, c.y, c.z, -cx(i), -cy(i), -cz(i), rx, ry, rz);
+            sdir[i] = dir_index(-rx, -ry, -rz);
+        }
+    }
 
     T d[Q];
     d[0] = C::load(base + n);
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
         if (PAR == 0) {
-            // wall: the redirected f*_opp(i)(x) sits in (i, x)
-            const uint32_t off = src[i] < 0 ? uint32_t(i * N + n) : uint32_t(opp(i) * N + src[i]);
+            // no-slip wall: the redirected f*_opp(i)(x) sits in (i, x); free-slip
+            // wall: f*_sdir(src) sits in (opp(sdir), src) like any layout-A value
+            const uint32_t off = src[i] < 0 ? uint32_t(i * N + n) : uint32_t(opp(sdir[i]) * N + src[i]);
             d[i] = C::load(base + off);
         } else {
             d[i] = C::load(base + i * N + n);
@@ -399,7 +415,7 @@ __device__ __forceinline__ bool update_cell(const StepArgs &a, const long long g
     }
 
     bool marked = false;
-    if (IF) marked = interface_part<ST, PAR>(a, gid, fl, c, src, d);
+    if (IF) marked = interface_part<ST, PAR, SLIPC>(a, gid, fl, c, src, d);
 
     const double *gr = a.grav + 3 * c.b;
     const T om = T(a.omega[c.b]);
@@ -415,8 +431,14 @@ __device__ __forceinline__ bool update_cell(const StepArgs &a, const long long g
     for (int i = 1; i < Q; ++i) {
         if (PAR == 0) {
             int t = nbl(cx(i), cy(i), cz(i));
-            // a wall neighbour gets the bounce-back slot (opp(i), x) instead
-            const uint32_t off = t < 0 ? uint32_t(opp(i) * N + n) : uint32_t(i * N + t);
+            // a no-slip wall neighbour gets the bounce-back slot (opp(i), x)
+            // instead; a free-slip one the arrival slot of the reflection
+            uint32_t off = t < 0 ? uint32_t(opp(i) * N + n) : uint32_t(i * N + t);
+            if (SLIPC && t < 0) {
+                int rx, ry, rz;
+                const int m = slip_target(g, c.x, c.y, c.z, cx(i), cy(i), cz(i), rx, ry, rz);
+                off = uint32_t(dir_index(rx, ry, rz) * N + m);
+            }
             C::store(base + off, d[i]);
         } else {
             C::store(base + opp(i) * N + n, d[i]);
@@ -601,7 +623,7 @@ __global__ __launch_bounds__(256) void k_resolve(StepArgs a) {
 // Lane j in 1..18 loads neighbour x + c_j; lane i in 0..18 produces f_i.
 // Returns nothing; writes the populations in the layout after this step and
 // the cell's outgoing copy, and sets m = 0.
-template <int ST, int SCHEME>
+template <int ST, int SCHEME, int SLIP>
 __device__ __forceinline__ void refill_group(const StepArgs &a, const long long gid, const int lane,
                                              const bool active) {
     const int layoutB = 1 - a.parity;   // layout after this step
@@ -619,7 +641,7 @@ __device__ __forceinline__ void refill_group(const StepArgs &a, const long long 
     const long long qg = cbase + (q >= 0 ? q : c.n);
     const uint8_t fq = a.flags[qg];
     double d[Q];
-    load_cell<ST>(a, layoutB, decode(a.g, qg), d);
+    load_cell<ST, SLIP>(a, layoutB, decode(a.g, qg), d);
     issue_fence();
     const bool valid = q >= 0 && refill_source(fq);
     double r, ux, uy, uz;
@@ -676,9 +698,9 @@ __device__ __forceinline__ void refill_group(const StepArgs &a, const long long 
             const int k3 = v2 ? nb_local(a.g, c2.x, c2.y, c2.z, ddx, ddy, ddz) : -1;
             const bool v3 = k3 >= 0 && refill_source(a.flags[cbase + k3]);
             const Cell c3 = decode(a.g, cbase + (v3 ? k3 : k1));
-            const double f1 = load_slot<ST>(a, slot_flat_rt(a.g, layoutB, c1, i));
-            const double f2 = load_slot<ST>(a, slot_flat_rt(a.g, layoutB, c2, i));
-            const double f3 = load_slot<ST>(a, slot_flat_rt(a.g, layoutB, c3, i));
+            const double f1 = load_slot<ST>(a, slot_flat_rt<SLIP>(a.g, layoutB, c1, i));
+            const double f2 = load_slot<ST>(a, slot_flat_rt<SLIP>(a.g, layoutB, c2, i));
+            const double f3 = load_slot<ST>(a, slot_flat_rt<SLIP>(a.g, layoutB, c3, i));
             out = (v2 && v3) ? 3.0 * f1 - 3.0 * f2 + f3 : (v2 ? 2.0 * f1 - f2 : f1);
         }
     } else if (SCHEME == 2) {
@@ -729,7 +751,7 @@ __device__ __forceinline__ void refill_group(const StepArgs &a, const long long 
         if (nv > 0.0) out = mine / nv;
     }
     if (active && lane < Q) {
-        store_slot<ST>(a, slot_flat_rt(a.g, layoutB, c, i), out);
+        store_slot<ST>(a, slot_flat_rt<SLIP>(a.g, layoutB, c, i), out);
         if (i > 0) store_fo<ST>(a, i, gid, out);
     }
     // density after this step: the stored populations summed in direction order
@@ -746,9 +768,9 @@ __device__ __forceinline__ void refill_group(const StepArgs &a, const long long 
 
 // Density sum_i f*_i of a cell in the layout after this step, also returned
 // as shifted populations.
-template <int ST>
+template <int ST, int SLIP>
 __device__ __forceinline__ double rho_after(const StepArgs &a, const Cell &c, double (&d)[Q]) {
-    load_cell<ST>(a, 1 - a.parity, c, d);
+    load_cell<ST, SLIP>(a, 1 - a.parity, c, d);
     double s = 0.0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) s += d[i];
@@ -763,7 +785,7 @@ __device__ __forceinline__ double rho_after(const StepArgs &a, const Cell &c, do
 // density).  The per-domain interface counts are corrected on the way.  The
 // new cells keep their gas-typed flag until k_excess, so the refill sources
 // read the same validity throughout.
-template <int ST, int SCHEME>
+template <int ST, int SCHEME, int SLIP>
 __global__ __launch_bounds__(256) void k_convert(StepArgs a) {
     const int p = a.parity;
     const long long N = a.g.N;
@@ -782,7 +804,7 @@ __global__ __launch_bounds__(256) void k_convert(StepArgs a) {
             const long long cell = t >> 5;
             const bool active = in && cell < nng;
             const long long g0 = active ? a.list_newg[cell] : 0;
-            refill_group<ST, SCHEME>(a, g0, int(t & 31), active);
+            refill_group<ST, SCHEME, SLIP>(a, g0, int(t & 31), active);
             gid = g0;
             if (active && (t & 31) == 0) {
                 // a new interface cell may sit in a tile that never held fluid
@@ -804,7 +826,7 @@ __global__ __launch_bounds__(256) void k_convert(StepArgs a) {
 #pragma unroll
                     for (int i = 1; i < Q; ++i) fq[i] = a.flags[cbase + (nb[i] >= 0 ? nb[i] : c.n)];
                     double d[Q];
-                    const double mx = fill ? a.m[gid] - rho_after<ST>(a, c, d) : a.m[gid];
+                    const double mx = fill ? a.m[gid] - rho_after<ST, SLIP>(a, c, d) : a.m[gid];
                     int nr = 0;
                     uint32_t recv = 0;
 #pragma unroll
@@ -834,7 +856,7 @@ __global__ __launch_bounds__(256) void k_convert(StepArgs a) {
             } else {
                 // from liquid: mass = density; keep a copy of its populations
                 double d[Q];
-                const double rho = rho_after<ST>(a, c, d);
+                const double rho = rho_after<ST, SLIP>(a, c, d);
                 a.m[gid] = rho;
                 a.rho_if[gid] = rho;
 #pragma unroll
@@ -1017,15 +1039,19 @@ static void launch_bulk_t(const StepArgs &a, const StepArgs *pending, hipStream_
 template <int ST, typename F>
 static void launch_coll(int coll, int parity, F &&f) {
     using std::integral_constant;
-    switch (coll * 2 + parity) {
-        case 0: f(integral_constant<int, 0>{}, integral_constant<int, 0>{}); break;
-        case 1: f(integral_constant<int, 0>{}, integral_constant<int, 1>{}); break;
-        case 2: f(integral_constant<int, 1>{}, integral_constant<int, 0>{}); break;
-        case 3: f(integral_constant<int, 1>{}, integral_constant<int, 1>{}); break;
-        case 4: f(integral_constant<int, 2>{}, integral_constant<int, 0>{}); break;
-        case 5: f(integral_constant<int, 2>{}, integral_constant<int, 1>{}); break;
-        case 6: f(integral_constant<int, 3>{}, integral_constant<int, 0>{}); break;
-        default: f(integral_constant<int, 3>{}, integral_constant<int, 1>{}); break;
+    auto par = [&](auto C) {
+        if (parity == 0) f(C, integral_constant<int, 0>{});
+        else f(C, integral_constant<int, 1>{});
+    };
+    switch (coll) {
+        case 0: par(integral_constant<int, 0>{}); break;
+        case 1: par(integral_constant<int, 1>{}); break;
+        case 2: par(integral_constant<int, 2>{}); break;
+        case 3: par(integral_constant<int, 3>{}); break;
+        case 4: par(integral_constant<int, 4>{}); break;
+        case 5: par(integral_constant<int, 5>{}); break;
+        case 6: par(integral_constant<int, 6>{}); break;
+        default: par(integral_constant<int, 7>{}); break;
     }
 }
 
@@ -1043,8 +1069,9 @@ static void launch_step_t(const StepArgs &a, int collision, int scheme, hipStrea
         hipLaunchKernelGGL(k_curvature, dim3(lb), dim3(256), 0, s, a);
     }
     if (ev) (void)hipEventRecord(ev->before, s);
-    // collision variant: bit 0 TRT, bit 1 Smagorinsky turbulence model
-    const int coll = (collision ? 1 : 0) | (a.les_k > 0.0 ? 2 : 0);
+    // collision variant: bit 0 TRT, bit 1 Smagorinsky turbulence model, bit 2
+    // free-slip walls
+    const int coll = (collision ? 1 : 0) | (a.les_k > 0.0 ? 2 : 0) | (a.g.slip ? 4 : 0);
     launch_coll<ST>(coll, a.parity, [&](auto C, auto P) {
         launch_bulk_t<ST, decltype(C)::value, decltype(P)::value>(a, pending, s);
     });
@@ -1054,13 +1081,18 @@ static void launch_step_t(const StepArgs &a, int collision, int scheme, hipStrea
                            s, a);
     });
     hipLaunchKernelGGL(k_resolve, dim3(lb), dim3(256), 0, s, a);
-    switch (scheme) {
-        case 0: hipLaunchKernelGGL((k_convert<ST, 0>), dim3(lb), dim3(256), 0, s, a); break;
-        case 1: hipLaunchKernelGGL((k_convert<ST, 1>), dim3(lb), dim3(256), 0, s, a); break;
-        case 2: hipLaunchKernelGGL((k_convert<ST, 2>), dim3(lb), dim3(256), 0, s, a); break;
-        case 3: hipLaunchKernelGGL((k_convert<ST, 3>), dim3(lb), dim3(256), 0, s, a); break;
-        default: hipLaunchKernelGGL((k_convert<ST, 4>), dim3(lb), dim3(256), 0, s, a); break;
-    }
+    auto convert = [&](auto SL) {
+        constexpr int SLIP = decltype(SL)::value;
+        switch (scheme) {
+            case 0: hipLaunchKernelGGL((k_convert<ST, 0, SLIP>), dim3(lb), dim3(256), 0, s, a); break;
+            case 1: hipLaunchKernelGGL((k_convert<ST, 1, SLIP>), dim3(lb), dim3(256), 0, s, a); break;
+            case 2: hipLaunchKernelGGL((k_convert<ST, 2, SLIP>), dim3(lb), dim3(256), 0, s, a); break;
+            case 3: hipLaunchKernelGGL((k_convert<ST, 3, SLIP>), dim3(lb), dim3(256), 0, s, a); break;
+            default: hipLaunchKernelGGL((k_convert<ST, 4, SLIP>), dim3(lb), dim3(256), 0, s, a); break;
+        }
+    };
+    if (a.g.slip) convert(std::integral_constant<int, 1>{});
+    else convert(std::integral_constant<int, 0>{});
     if (finish) hipLaunchKernelGGL(k_excess<ST>, dim3(lb), dim3(256), 0, s, a);
 }
 

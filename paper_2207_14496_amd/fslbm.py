@@ -49,7 +49,7 @@ class CParams(ctypes.Structure):
                 ("sigma", ctypes.c_double), ("p_volume", ctypes.c_double),
                 ("eps_phi", ctypes.c_double), ("omega_b", ctypes.POINTER(ctypes.c_double)),
                 ("gravity_b", ctypes.POINTER(ctypes.c_double)), ("stream", ctypes.c_void_p),
-                ("smagorinsky_cs", ctypes.c_double)]
+                ("smagorinsky_cs", ctypes.c_double), ("free_slip", ctypes.c_int32)]
 
 
 class CDiag(ctypes.Structure):
@@ -130,6 +130,7 @@ class Params:
     omega_b: tuple | None = None      # per-domain omega [B]
     gravity_b: tuple | None = None    # per-domain gravity [B][3]
     smagorinsky_cs: float = 0.0       # Smagorinsky constant (0 = no turbulence model)
+    free_slip: int = 0                # walls: 0 no-slip, 1 free-slip (specular)
 
     @property
     def N(self) -> int:
@@ -145,6 +146,7 @@ class Params:
         p.omega, p.trt_lambda = float(self.omega), float(self.trt_lambda)
         p.sigma, p.p_volume, p.eps_phi = float(self.sigma), float(self.p_volume), float(self.eps_phi)
         p.smagorinsky_cs = float(self.smagorinsky_cs)
+        p.free_slip = int(self.free_slip)
         keep = []
         if self.omega_b is not None:
             arr = (ctypes.c_double * self.batch)(*[float(v) for v in self.omega_b])

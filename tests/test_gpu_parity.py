@@ -125,6 +125,37 @@ def test_smagorinsky_dam_break_multi_step_calls():
     sim.close()
 
 
+@pytest.mark.parametrize("collision", [0, 1])
+def test_free_slip_random_states(collision):
+    """Free-slip (specular) walls on two and three axes: random interface
+    states, three steps (populations reflected into neighbouring cells, the
+    mass exchange along the reflected links, anti-bounce-back from gas found
+    there)."""
+    for seed, periodic in ((40 + collision, (0, 1, 0)), (50 + collision, (0, 0, 0))):
+        s = setups.random_interface_state(12, 10, 9, seed, periodic=periodic, g=(0.0, 0.0, -1e-4),
+                                          collision=collision)
+        p = oracle_params(s, free_slip=1)
+        st = oracle_state(s, p)
+        announce(f"free-slip random state seed {seed} periodic {periodic}")
+        _run_pair(p, st, 3, f"free-slip seed {seed}")
+
+
+@pytest.mark.parametrize("scheme", [0, 1, 2, 4])
+def test_free_slip_dam_break_multi_step_calls(scheme):
+    """The paper's dam-break walls (free-slip) with its turbulence model at a
+    high relaxation rate: the small dam break, eight steps per call."""
+    s = setups.rect_dam_break(40, 6, 24, width=12, height=16, g=2e-4, refill=scheme, omega=1.99)
+    p = oracle_params(s, free_slip=1, smag_cs=0.1)
+    st = oracle_state(s, p)
+    announce(f"free-slip + Smagorinsky dam break scheme {scheme}")
+    sim = sim_from_states(p, [st])
+    for k in range(5):
+        sim.step(8)
+        oracle.step(p, st, 8)
+        compare(fields_np(sim), 0, st, 1e-11, 1e-11, 1e-11, what=f"free-slip dam break step {8 * (k + 1)}")
+    sim.close()
+
+
 def test_surface_tension_drop():
     """Curvature path: a small 3-D drop with surface tension (sigma != 0)."""
     n = 20
