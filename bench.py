@@ -26,8 +26,9 @@ gravity_wave_schemes  (--gravity-wave-schemes) the same wave at L = 800 (FP64)
            with each refilling scheme, next to the per-scheme series the paper prints.
 dam_break  rectangular dam break 256 x 128 x 64 (FP32), each refilling scheme,
            20000 steps: front position, residual height, stability, mass drift.
-dam_break_les  the same at the paper's omega = 1.9995 with its Smagorinsky
-           turbulence model (C_S = 0.1).
+paper_dam_break  the rectangular dam break as the paper sets it up (Sec. 4.2):
+           15W x 2H, H = 2W, W = 50, SRT omega = 1.9995, Smagorinsky C_S = 0.1,
+           free-slip walls, each refilling scheme: w*(t*), h*(t*), stability.
 drop_impact  drop impact 256^3 with surface tension, every storage type, 8000
            steps: centre-column height, cavity depth, mass drift, and the
            fill-level / flag differences against the FP64 run.
@@ -221,9 +222,7 @@ def main():
         result["gravity_wave_schemes"] = gravity_wave_schemes(fslbm)
     if not args.no_reports:
         result["dam_break"] = dam_break_report(fslbm, setups, torch, args.dam_break_steps)
-        # the paper's dam-break relaxation rate, runnable with its turbulence model
-        result["dam_break_les"] = dam_break_report(fslbm, setups, torch, args.dam_break_steps,
-                                                   omega=1.9995, smagorinsky_cs=0.1)
+        result["paper_dam_break"] = paper_dam_break_report(fslbm, setups, torch)
         result["drop_impact"] = drop_impact_report(fslbm, setups, torch, args.drop_steps)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
@@ -279,19 +278,21 @@ def gravity_wave_schemes(fslbm, L=800, t_star_end=15.0):
     return out
 
 
-def dam_break_report(fslbm, setups, torch, steps, every=1000, omega=1.95, smagorinsky_cs=0.0):
+def dam_break_report(fslbm, setups, torch, steps, every=1000, omega=1.95, smagorinsky_cs=0.0,
+                     free_slip=0):
     """Rectangular dam break 256x128x64 (FP32 storage), each refilling scheme:
     front position and residual height every `every` steps in cells and in the
     paper's dimensionless form (w* = front / W, h* = height / H, t* = t sqrt(2 g / W),
     Sec. 4.2), the first check at which the run was unstable, and the mass drift.
-    omega / smagorinsky_cs: the relaxation rate and the turbulence model."""
+    omega / smagorinsky_cs / free_slip: the relaxation rate, the turbulence
+    model and the wall condition."""
     import math
     from paper_2207_14496_amd import observe
     out = []
     for scheme, name in enumerate(("EQ", "EQ+NEQ", "GEQ", "EXT", "AVG")):
         s = setups.rect_dam_break(refill=scheme, omega=omega)
         W, H, g = s.meta["width"], s.meta["height"], abs(s.g[2])
-        sim = fslbm.from_setup(s, storage=fslbm.F32, smagorinsky_cs=smagorinsky_cs)
+        sim = fslbm.from_setup(s, storage=fslbm.F32, smagorinsky_cs=smagorinsky_cs, free_slip=free_slip)
         m0 = sim.diagnostics()[0]["total_mass"]
         series, unstable_at, done, t0 = [], None, 0, time.perf_counter()
         while done < steps:
@@ -320,8 +321,52 @@ def dam_break_report(fslbm, setups, torch, steps, every=1000, omega=1.95, smagor
         log(f"  dam break {name} (omega {omega}, C_S {smagorinsky_cs}): {done} steps, "
             f"unstable at {unstable_at}, last {last}")
     return {"workload": f"rect-dam-break 256x128x64 D3Q19 TRT omega={omega} g=2e-5, f32 shifted PDFs"
-                        + (f", Smagorinsky C_S={smagorinsky_cs}" if smagorinsky_cs else ""),
+                        + (f", Smagorinsky C_S={smagorinsky_cs}" if smagorinsky_cs else "")
+                        + (", free-slip walls" if free_slip else ", no-slip walls"),
             "schemes": out}
+
+
+def paper_dam_break_report(fslbm, setups, torch, W=50, t_star_end=8.0, dt_star=0.25):
+    """The rectangular dam break as the paper sets it up (Sec. 4.2): 15W x 2H,
+    H = 2W, W = 50, SRT omega = 1.9995 with the Smagorinsky model (C_S = 0.1),
+    free-slip walls, FP64; each refilling scheme until the front reaches 14 W
+    (w* >= 14) or t* = t_star_end: w*(t*) and h*(t*) every dt_star, and whether
+    the run stayed stable."""
+    import math
+    from paper_2207_14496_amd import observe
+    out = []
+    for scheme, name in enumerate(("EQ", "EQ+NEQ", "GEQ", "EXT", "AVG")):
+        s = setups.paper_dam_break(W=W, refill=scheme)
+        H, g = s.meta["height"], s.meta["g"]
+        sim = fslbm.from_setup(s, storage=fslbm.F64, smagorinsky_cs=0.1, free_slip=1)
+        m0 = sim.diagnostics()[0]["total_mass"]
+        unit = math.sqrt(2.0 * g / W)               # t* per step
+        every = max(1, int(round(dt_star / unit)))
+        series, done, unstable_at, t0 = [], 0, None, time.perf_counter()
+        while done * unit < t_star_end:
+            sim.step(every)
+            done += every
+            d = sim.diagnostics()[0]
+            if not d["stable"]:
+                unstable_at = round(done * unit, 3)
+                break
+            fl = sim.read(("flags",))["flags"][0]
+            wst = observe.front_position(fl, s.nx, s.ny, s.nz) / W
+            hst = observe.residual_height(fl, s.nx, s.ny, s.nz) / H
+            series.append([round(done * unit, 3), round(wst, 3), round(hst, 4)])
+            if wst >= 14.0:
+                break
+        rec = {"scheme": name, "steps_run": done, "unstable_at_t_star": unstable_at,
+               "mass_drift_rel": (d["total_mass"] - m0) / m0 if unstable_at is None else None,
+               "series": series, "series_columns": ["t*", "w*", "h*"],
+               "wall_s": round(time.perf_counter() - t0, 2)}
+        sim.close()
+        torch.cuda.empty_cache()
+        out.append(rec)
+        log(f"  paper dam break W={W} {name}: {done} steps, unstable at t* {unstable_at}, "
+            f"last {series[-1] if series else None}")
+    return {"workload": f"paper-dam-break {15 * W}x1x{4 * W}, W={W}, H=2W, D3Q19 SRT omega=1.9995, "
+                        f"Smagorinsky C_S=0.1, free-slip walls, Ga=1.83e9, f64", "schemes": out}
 
 
 def drop_impact_report(fslbm, setups, torch, steps, every=1000):

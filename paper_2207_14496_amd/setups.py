@@ -215,10 +215,10 @@ def gravity_wave(L=200, reynolds=10.0, omega=1.8, refill=0, name="gravity-wave")
 
 
 def rect_dam_break(nx=256, ny=128, nz=64, width=64, height=32, omega=1.95, g=2e-5,
-                   refill=0, name="rect-dam-break") -> Setup:
+                   refill=0, name="rect-dam-break", collision=1) -> Setup:
     """Rectangular dam break: liquid box x < width, z < height, all y, against the
-    x = 0 wall; walls on all sides; gravity -g along z; TRT; hydrostatic."""
-    s = Setup(name, nx, ny, nz, (0, 0, 0), 1, omega, (0.0, 0.0, -g), refill=refill)
+    x = 0 wall; walls on all sides; gravity -g along z; TRT (or SRT); hydrostatic."""
+    s = Setup(name, nx, ny, nz, (0, 0, 0), collision, omega, (0.0, 0.0, -g), refill=refill)
     zc = _centres(nz)[:, None, None]
     xc = _centres(nx)[None, None, :]
     phi3 = np.broadcast_to(((zc < height) & (xc < width)).astype(np.float64), (nz, ny, nx)).copy()
@@ -226,6 +226,21 @@ def rect_dam_break(nx=256, ny=128, nz=64, width=64, height=32, omega=1.95, g=2e-
     rho3 = np.broadcast_to(1.0 + 3.0 * g * (height - zc), (nz, ny, nx)).copy()
     s.meta = dict(width=width, height=height)
     return _finish(s, phi3, rho3)
+
+
+def paper_dam_break(W=50, omega=1.9995, galilei=1.83e9, refill=0) -> Setup:
+    """The rectangular dam break of Sec. 4.2 as the paper sets it up: a liquid
+    column of width W and height H = 2W at the x = 0 wall of a 15W x 2H domain,
+    one cell thick in y (with free-slip walls this is a two-dimensional flow),
+    SRT at omega = 1.9995, g along -z from the Galilei number Ga = g W^3 / nu^2,
+    hydrostatic.  The run is meant with free-slip walls and the Smagorinsky
+    model (C_S = 0.1), which are library parameters."""
+    nu = (1.0 / omega - 0.5) / 3.0
+    g = galilei * nu * nu / W ** 3
+    s = rect_dam_break(nx=15 * W, ny=1, nz=4 * W, width=W, height=2 * W, omega=omega, g=g,
+                       refill=refill, name="paper-dam-break", collision=0)
+    s.meta.update(nu=nu, g=g)
+    return s
 
 
 def drop_impact(n=256, pool_depth=64, radius=16.0, drop_centre_z=104.0, drop_u=0.02,

@@ -156,6 +156,23 @@ def test_free_slip_dam_break_multi_step_calls(scheme):
     sim.close()
 
 
+@pytest.mark.parametrize("scheme", [0, 1, 2, 3, 4])
+def test_paper_dam_break_multi_step_calls(scheme):
+    """The dam break as the paper runs it (Sec. 4.2): 750 x 1 x 200, one cell
+    layer between free-slip walls, SRT at omega = 1.9995 with the turbulence
+    model, gravity from Ga = 1.83e9; three calls of eight steps."""
+    s = setups.paper_dam_break(W=50, refill=scheme)
+    p = oracle_params(s, free_slip=1, smag_cs=0.1)
+    st = oracle_state(s, p)
+    announce(f"paper dam break 750x1x200 scheme {scheme}")
+    sim = sim_from_states(p, [st])
+    for k in range(3):
+        sim.step(8)
+        oracle.step(p, st, 8)
+        compare(fields_np(sim), 0, st, 1e-11, 1e-11, 1e-11, what=f"paper dam break step {8 * (k + 1)}")
+    sim.close()
+
+
 def test_surface_tension_drop():
     """Curvature path: a small 3-D drop with surface tension (sigma != 0)."""
     n = 20

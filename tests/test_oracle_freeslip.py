@@ -85,3 +85,43 @@ def test_free_surface_mass_with_free_slip_walls(scheme):
     m1 = oracle.total_mass(p, st)
     assert abs(m1 - m0) <= 1e-12 * m0
     assert st.counts is not None
+
+
+def test_paper_dam_break_setup():
+    """The Sec. 4.2 dam break: 15W x 1 x 2H with H = 2W, the column W x H at
+    x = 0, SRT, and gravity from the Galilei number Ga = g W^3 / nu^2 with the
+    lattice viscosity nu = (1/omega - 1/2) / 3."""
+    W, omega, Ga = 50, 1.9995, 1.83e9
+    s = setups.paper_dam_break(W=W)
+    assert (s.nx, s.ny, s.nz) == (15 * W, 1, 4 * W) and s.collision == 0 and s.omega == omega
+    nu = (1.0 / omega - 0.5) / 3.0
+    assert abs(-s.g[2] * W ** 3 / nu ** 2 / Ga - 1.0) < 1e-14 and s.g[:2] == (0.0, 0.0)
+    phi = s.phi.reshape(s.nz, s.ny, s.nx)
+    assert phi[: 2 * W - 1, 0, : W - 1].min() == 1.0       # inside the column
+    assert phi[2 * W + 1:, 0, :].max() == 0.0 and phi[:, 0, W + 1:].max() == 0.0
+    assert abs(phi.sum() - W * 2 * W) <= 1.0                # its volume, up to the top layer
+
+
+def test_single_cell_layer_between_free_slip_walls_stays_mirror_symmetric():
+    """One cell layer between free-slip walls in y (the paper's two-dimensional
+    dam break): a population moving up in y is reflected into the one moving
+    down, so a y-symmetric start stays y-symmetric, f_i = f_mirror(i) up to
+    rounding; mass is conserved; the column collapses (the front advances).
+    Small dam break with the turbulence model, 150 steps."""
+    s = setups.paper_dam_break(W=10, galilei=5.8e7)
+    p = oracle_params(s, free_slip=1, smag_cs=0.1)
+    st = oracle_state(s, p)
+    m0 = oracle.total_mass(p, st)
+    oracle.step(p, st, 150)
+    fluid = st.flags != 4
+    np.testing.assert_allclose(st.f[MIRROR_Y][:, fluid], st.f[:, fluid], rtol=0, atol=1e-14)
+    assert abs(oracle.total_mass(p, st) - m0) <= 1e-12 * m0
+    fl = st.flags.reshape(s.nz, s.nx)
+    assert np.nonzero(fl[0] != 4)[0].max() + 1 > 12
+    # a y-asymmetric start does not stay symmetric by accident: the test sees
+    # a sign error in the reflection
+    st2 = oracle_state(s, p)
+    st2.f[3] += 1e-4 * (st2.flags != 4)
+    oracle.step(p, st2, 5)
+    fluid = st2.flags != 4
+    assert np.abs(st2.f[MIRROR_Y][:, fluid] - st2.f[:, fluid]).max() > 1e-7
