@@ -199,8 +199,6 @@ __device__ __forceinline__ int dir_index(int x, int y, int z) {
 // Flat index of the slot holding f*_i of cell c in the given layout (after
 // an odd number of steps a population that went into a free-slip wall sits
 // in its reflected arrival slot), for a runtime direction i.
-__device__ __forceinline__ int dir_index(int x, int y, int z);
-
 // SLIP: 1 free-slip walls, 0 no-slip walls, -1 as the geometry says (the
 // kernels that run every step fix it at compile time).
 template <int SLIP = -1>
