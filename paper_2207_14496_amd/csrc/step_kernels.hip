@@ -280,15 +280,22 @@ __device__ __forceinline__ bool interface_part(const StepArgs &a, const long lon
     const long long cbase = (long long)c.b * N;
     const typename C::M *fob = static_cast<const typename C::M *>(a.fo);
     // own outgoing populations f*_i(x, t), i = 1..18, and neighbour flags
+    // (every load of a round is issued before the first use; the fences keep
+    // the compiler from sinking loads into the branches that use them, where
+    // each would wait on its own)
     T fo[Q];
     uint8_t fn[Q];   // flag of the cell x - c_i (source of direction i)
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
         fo[i] = C::load(fob + fo_index(gid, i));
-        fn[i] = src[i] >= 0 ? a.flags[cbase + src[i]] : uint8_t(0);
+        fn[i] = a.flags[cbase + (src[i] >= 0 ? src[i] : c.n)];   // own flag at walls: unused
     }
     const double m0 = a.m[gid];
     const double phx = a.phi_cur[gid];
+    const double rg = a.rhoG ? a.rhoG[gid] : 3.0 * a.p_volume;
+    issue_fence();
+#pragma unroll
+    for (int i = 1; i < Q; ++i) fn[i] = src[i] >= 0 ? fn[i] : uint8_t(0);
     // mass exchange: the neighbour x + c_i is the source of direction opp(i)
     const int cc = fclass(fl);
     // fill levels of the interface neighbours, all loads in flight together
@@ -300,6 +307,7 @@ __device__ __forceinline__ bool interface_part(const StepArgs &a, const long lon
         const bool itf = src[o] >= 0 && !(fn[o] & (F_GAS | F_LIQ));
         phn[i] = a.phi_cur[itf ? cbase + src[o] : gid];
     }
+    issue_fence();
     double dm = 0.0;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
@@ -328,7 +336,6 @@ __device__ __forceinline__ bool interface_part(const StepArgs &a, const long lon
     }
     const double *gr = a.grav + 3 * c.b;
     const double ux = jx / r0 - 0.5 * gr[0], uy = jy / r0 - 0.5 * gr[1], uz = jz / r0 - 0.5 * gr[2];
-    const double rg = a.rhoG ? a.rhoG[gid] : 3.0 * a.p_volume;
     const double uu = ux * ux + uy * uy + uz * uz;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
