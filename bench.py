@@ -32,6 +32,9 @@ paper_dam_break  the rectangular dam break as the paper sets it up (Sec. 4.2):
 drop_impact  drop impact 256^3 with surface tension, every storage type, 8000
            steps: centre-column height, cavity depth, mass drift, and the
            fill-level / flag differences against the FP64 run.
+adjoint    the reverse mode at full size (64 domains of the 128 x 256 standing
+           wave, 4000 steps, sqrt(T) checkpoints): forward and backward wall
+           time and cell updates per second.
 """
 from __future__ import annotations
 
@@ -153,13 +156,15 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--variant-steps", type=int, default=300)
     ap.add_argument("--no-reports", action="store_true",
-                    help="skip the rectangular dam break and drop impact reports")
+                    help="skip the configuration reports (dam breaks, drop impact, adjoint)")
     ap.add_argument("--dam-break-steps", type=int, default=20000)
     ap.add_argument("--gravity-wave-schemes", action="store_true",
                     help="also run the L = 800 gravity wave with every refilling scheme (about 3 min)")
     ap.add_argument("--drop-steps", type=int, default=8000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB elementwise copy kernel 5 times (HBM counter calibration)")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only run the reverse-mode report (64 x 128x256, 4000 steps) and print it")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -176,6 +181,10 @@ def main():
             torch.mul(src, 2.0, out=dst)   # one elementwise kernel: reads and writes 1 GiB
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_per_dispatch": 1 << 30, "dispatches": 5}), flush=True)
+        return
+    if args.adjoint_only:
+        from paper_2207_14496_amd import fslbm, setups
+        print(json.dumps({"adjoint": adjoint_report(fslbm, setups, torch)}), flush=True)
         return
     from paper_2207_14496_amd import fslbm, setups
 
@@ -224,6 +233,7 @@ def main():
         result["dam_break"] = dam_break_report(fslbm, setups, torch, args.dam_break_steps)
         result["paper_dam_break"] = paper_dam_break_report(fslbm, setups, torch)
         result["drop_impact"] = drop_impact_report(fslbm, setups, torch, args.drop_steps)
+        result["adjoint"] = adjoint_report(fslbm, setups, torch)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
         result["cpu_baseline"] = cpu_baseline(setup)
@@ -367,6 +377,51 @@ def paper_dam_break_report(fslbm, setups, torch, W=50, t_star_end=8.0, dt_star=0
             f"last {series[-1] if series else None}")
     return {"workload": f"paper-dam-break {15 * W}x1x{4 * W}, W={W}, H=2W, D3Q19 SRT omega=1.9995, "
                         f"Smagorinsky C_S=0.1, free-slip walls, Ga=1.83e9, f64", "schemes": out}
+
+
+def adjoint_report(fslbm, setups, torch, T=4000, B=64, x_probe=32):
+    """Reverse mode at its full configuration: the 128 x 256 standing wave
+    (FP64, SRT, EQ refilling), B seeded domains in one launch, a loss window of
+    T steps with ceil(sqrt(T)) checkpoints.  Wall time of the checkpointed
+    forward (T steps, records, heights) and of the backward (each segment
+    recomputed from its record, then the reverse steps), the cell updates per
+    second of each, and the workspace size.  The target only changes the loss
+    value, not the work, so h* = 0 is used."""
+    import numpy as np
+    from paper_2207_14496_amd import adjoint
+    nx, ny, depth, a0v, om, gv = 128, 256, 128.0, 1.28, 1.8, 1e-5
+    pert = [setups.target_perturbation(s) for s in range(B)]
+    a0 = torch.tensor([a0v * (1 + p[2]) for p in pert], dtype=torch.float64, device="cuda")
+    flags, pdf0, mass0, phi0 = adjoint.standing_wave_state(a0, nx, ny, depth)
+    params = fslbm.Params(nx, ny, 1, B, (1, 0, 1), fslbm.SRT, fslbm.F64, fslbm.REFILL_EQ, om,
+                          omega_b=[om * (1 + p[0]) for p in pert],
+                          gravity_b=[(0.0, -gv * (1 + p[1]), 0.0) for p in pert])
+    sim = fslbm.Simulation(params, flags, phi0, pdf=pdf0, mass=mass0)
+    target = np.zeros((B, T))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss, _ = sim.adjoint_forward(target, T, x_probe)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    g = sim.adjoint_backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    ws = int(sim._adj[3])
+    finite = bool(np.all(np.isfinite(loss)) and np.all(np.isfinite(g["omega"]))
+                  and np.all(np.isfinite(g["gravity"])) and bool(torch.isfinite(g["phi"]).all()))
+    sim.close()
+    del g
+    torch.cuda.empty_cache()
+    updates = float(B) * nx * ny * T
+    fwd, bwd = t1 - t0, t2 - t1
+    log(f"  adjoint {B} x {nx}x{ny}, T={T}: forward {fwd:.2f} s, backward {bwd:.2f} s "
+        f"({updates / fwd / 1e6:.0f} / {updates / bwd / 1e6:.0f} MLUPS), workspace {ws / 1e9:.1f} GB")
+    return {"workload": f"adjoint standing wave {nx}x{ny}, {B} domains, T={T}, "
+                        f"ceil(sqrt(T)) checkpoints, FP64 SRT EQ",
+            "forward_s": round(fwd, 3), "backward_s": round(bwd, 3),
+            "backward_over_forward": round(bwd / fwd, 2),
+            "mlups_forward": round(updates / fwd / 1e6, 1), "mlups_backward": round(updates / bwd / 1e6, 1),
+            "workspace_gb": round(ws / 1e9, 2), "finite": finite}
 
 
 def drop_impact_report(fslbm, setups, torch, steps, every=1000):

@@ -99,9 +99,21 @@ __device__ __forceinline__ void stream_in(const AdjArgs &a, const Cell &c, doubl
     const double *f0 = a.s0.f;
     const uint8_t *fl = a.s0.fl;
     const long long cb = (long long)c.b * a.g.N;
-    double fs[Q];
+    // the cell's populations, and every source's flag and population, in one
+    // round of loads (the cell itself stands in for a wall source; unused)
+    double fs[Q], fp[Q];
+    int src[Q];
+    uint8_t fls[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) fs[i] = f0[pidx(a.g, c.b, i, c.n)];
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        src[i] = nb_local(a.g, c.x, c.y, c.z, -cx(i), -cy(i), -cz(i));
+        const int sc = src[i] < 0 ? c.n : src[i];
+        fls[i] = fl[cb + sc];
+        fp[i] = f0[pidx(a.g, c.b, i, sc)];
+    }
+    issue_fence();
     double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -114,14 +126,13 @@ __device__ __forceinline__ void stream_in(const AdjArgs &a, const Cell &c, doubl
     fin[0] = fs[0];
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-        const int s = nb_local(a.g, c.x, c.y, c.z, -cx(i), -cy(i), -cz(i));
-        if (s < 0) {
+        if (src[i] < 0) {
             fin[i] = fs[opp(i)];
-        } else if (fl[cb + s] == F_GAS) {
+        } else if (fls[i] == F_GAS) {
             const double uc = cx(i) * ux + cy(i) * uy + cz(i) * uz;
             fin[i] = 2.0 * wgt<double>(i) * a.rhoG * (1.0 + 4.5 * uc * uc - 1.5 * uu) - fs[opp(i)];
         } else {
-            fin[i] = f0[pidx(a.g, c.b, i, s)];
+            fin[i] = fp[i];
         }
     }
 }
@@ -325,7 +336,10 @@ __global__ __launch_bounds__(BS) void k_adj_collide(AdjArgs a) {
                 J[0] += cx(i) * fin[i]; J[1] += cy(i) * fin[i]; J[2] += cz(i) * fin[i];
             }
             const double F[3] = {rho * gr[0], rho * gr[1], rho * gr[2]};
-            const double u[3] = {J[0] / rho + 0.5 * gr[0], J[1] / rho + 0.5 * gr[1], J[2] / rho + 0.5 * gr[2]};
+            // one reciprocal for the many divisions by rho below (FP64
+            // division is a long instruction sequence on this part)
+            const double irho = 1.0 / rho;
+            const double u[3] = {J[0] * irho + 0.5 * gr[0], J[1] * irho + 0.5 * gr[1], J[2] * irho + 0.5 * gr[2]};
             const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
             const double uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
             const double pf = 1.0 - 0.5 * om;
@@ -342,7 +356,7 @@ __global__ __launch_bounds__(BS) void k_adj_collide(AdjArgs a) {
                 const double cF = ci[0] * F[0] + ci[1] * F[1] + ci[2] * F[2];
                 const double Fh = w * (3.0 * (cF - uF) + 9.0 * uc * cF);
                 lom += l * (-(fin[i] - feq) - 0.5 * Fh);
-                lrho += l * om * feq / rho;
+                lrho += l * om * feq * irho;
                 for (int d = 0; d < 3; ++d) {
                     lu[d] += l * (om * w * rho * (3.0 * ci[d] + 9.0 * uc * ci[d] - 3.0 * u[d]) +
                                   pf * w * (-3.0 * F[d] + 9.0 * ci[d] * cF));
@@ -350,26 +364,27 @@ __global__ __launch_bounds__(BS) void k_adj_collide(AdjArgs a) {
                 }
             }
             for (int d = 0; d < 3; ++d) lrho += lF[d] * gr[d];   // F = rho g
-            double lfi[Q];
+            // phi(t+1) = phi' = m' / rho on interface cells: its adjoint adds
+            // dr to every streamed population's adjoint
+            bool add_dr = false;
+            double dr = 0.0;
+            if (ty0 == F_IF) {
+                const double lp = a.lphis[gid];
+                if (lp != 0.0) {
+                    a.lmt[gid] += lp * irho;
+                    dr = -lp * a.s1.phi[gid] * irho;
+                    add_dr = true;
+                }
+            }
+            // (written out directly, not staged in registers: occupancy)
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 const int ci[3] = {cx(i), cy(i), cz(i)};
                 double v = (1.0 - om) * lam[i] + lrho;
-                for (int d = 0; d < 3; ++d) v += lu[d] * (ci[d] - (u[d] - 0.5 * gr[d])) / rho;
-                lfi[i] = v;
+                for (int d = 0; d < 3; ++d) v += lu[d] * (ci[d] - (u[d] - 0.5 * gr[d])) * irho;
+                if (add_dr) v += dr;
+                a.lfin[pidx(a.g, b, i, n)] = v;
             }
-            if (ty0 == F_IF) {
-                const double lp = a.lphis[gid];
-                if (lp != 0.0) {
-                    // phi(t+1) = phi' = m' / rho here
-                    a.lmt[gid] += lp / rho;
-                    const double dr = -lp * a.s1.phi[gid] / rho;
-#pragma unroll
-                    for (int i = 0; i < Q; ++i) lfi[i] += dr;
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < Q; ++i) a.lfin[pidx(a.g, b, i, n)] = lfi[i];
             acc[0] = lom;
             for (int d = 0; d < 3; ++d) acc[1 + d] = lF[d] * rho + 0.5 * lu[d];
         }
@@ -413,25 +428,40 @@ __global__ __launch_bounds__(BS) void k_adj_stream(AdjArgs a) {
             double out[Q];
             double lua[3] = {0.0, 0.0, 0.0};
             double lphi = 0.0;
+            // every neighbour's flag, the streamed adjoint there and the
+            // cell's own adjoint of the opposite direction, in one round of
+            // loads (the cell itself stands in for a wall neighbour; unused)
+            int nbx[Q];
+            uint8_t txs[Q];
+            double lnb[Q], lop[Q];
+#pragma unroll
+            for (int i = 1; i < Q; ++i) {
+                nbx[i] = nb_local(a.g, c.x, c.y, c.z, cx(i), cy(i), cz(i));   // y + c_i
+                const int xc = nbx[i] < 0 ? n : nbx[i];
+                txs[i] = a.s0.fl[cb + xc];
+                lnb[i] = a.lfin[pidx(a.g, b, i, xc)];
+                lop[i] = a.lfin[pidx(a.g, b, opp(i), n)];
+            }
+            issue_fence();
             out[0] = a.lfin[pidx(a.g, b, 0, n)];
 #pragma unroll
             for (int i = 1; i < Q; ++i) {
-                const int xn = nb_local(a.g, c.x, c.y, c.z, cx(i), cy(i), cz(i));   // y + c_i
-                const uint8_t tx = xn >= 0 ? a.s0.fl[cb + xn] : 0;
+                const int xn = nbx[i];
+                const uint8_t tx = xn >= 0 ? txs[i] : 0;
                 double v = 0.0;
                 if (xn < 0) {
-                    v = a.lfin[pidx(a.g, b, opp(i), n)];   // bounced back into y as opp(i)
+                    v = lop[i];   // bounced back into y as opp(i)
                 } else if (tx == F_GAS) {
                     // anti-bounce-back into y along opp(i) subtracts f*_i(y) and uses u(y)
                     const int o = opp(i);
-                    const double l = a.lfin[pidx(a.g, b, o, n)];
+                    const double l = lop[i];
                     v = -l;
                     const int co[3] = {cx(o), cy(o), cz(o)};
                     const double uc = co[0] * ua[0] + co[1] * ua[1] + co[2] * ua[2];
                     const double k2 = 2.0 * wgt<double>(o) * a.rhoG;
                     for (int d = 0; d < 3; ++d) lua[d] += l * k2 * (9.0 * uc * co[d] - 3.0 * ua[d]);
                 } else {
-                    v = a.lfin[pidx(a.g, b, i, xn)];   // streamed into y + c_i
+                    v = lnb[i];   // streamed into y + c_i
                     const double fin_y = a.s0.f[pidx(a.g, b, opp(i), xn)];   // f*_opp(i)(y + c_i)
                     const double fout_y = fs[i];                             // f*_i(y)
                     const double phx = a.s0.phi[cb + xn];

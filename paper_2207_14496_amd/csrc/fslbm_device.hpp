@@ -86,6 +86,11 @@ __device__ __forceinline__ typename Codec<ST>::T codec_round(typename Codec<ST>:
     return Codec<ST>::load(&m);
 }
 
+// Keeps the loads issued above it from being moved below it (into the
+// branches that use them), so that they are all in flight at once.  Emits no
+// instruction and no wait.
+__device__ __forceinline__ void issue_fence() { asm volatile("" ::: "memory"); }
+
 // ------------------------------------------------------------------ geometry
 // Unsigned division of n < 2^31 by an invariant d >= 1 with one 32x32->64
 // multiply and a shift (Granlund & Montgomery): m = ceil(2^(31+l) / d) with

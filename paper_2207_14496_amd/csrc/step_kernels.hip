@@ -50,11 +50,6 @@ namespace {   // every kernel has internal linkage; only the launchers are expor
          k##_it < k##_n; ++k##_it, k += k##_str)                                       \
         if (const bool in = k < k##_end; true)
 
-// Keeps the loads issued above it from being moved below it (into the
-// branches that use them), so that they are all in flight at once.  Emits no
-// instruction and no wait.
-__device__ __forceinline__ void issue_fence() { asm volatile("" ::: "memory"); }
-
 __device__ __forceinline__ long long clamp_cap(const StepArgs &a, int32_t v) {
     return v < a.cap ? (long long)v : a.cap;
 }
