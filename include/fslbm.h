@@ -176,10 +176,12 @@ fslbm_status fslbm_init(const fslbm_params *params, void *workspace, size_t byte
  * is the same. */
 fslbm_status fslbm_step(fslbm_ctx *ctx, int32_t nsteps);
 
-/* Run nsteps >= 1 full time steps (a)-(e) with direct kernel launches and HIP
- * events recorded on the context's stream right before and after the bulk
- * stream-collide kernel of every step (which, as in fslbm_step, also runs the
- * last step's excess-mass redistribution where that is fused).  Synchronises,
+/* Run nsteps >= 1 full time steps (a)-(e) with direct kernel launches on the
+ * context's stream; the bulk stream-collide kernel of every step (which, as in
+ * fslbm_step, also runs the last step's excess-mass redistribution where that
+ * is fused) is launched with start and stop HIP events stamped by its own
+ * dispatch (hipExtLaunchKernelGGL), so each duration is the kernel's alone.
+ * Synchronises,
  * then returns (HOST doubles, milliseconds) the summed duration of the bulk
  * kernels and the wall time of the whole sequence.  The state advances
  * exactly as fslbm_step. */

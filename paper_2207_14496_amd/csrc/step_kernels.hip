@@ -25,6 +25,8 @@
 // list kernels, so work that can share a kernel does.  Inside the list
 // kernels every load that does not depend on another is issued first, with
 // clamped in-bounds addresses for walls, and only then selected.
+#include <hip/hip_ext.h>
+
 #include <type_traits>
 
 #include "fslbm_kernels.hpp"
@@ -1027,11 +1029,20 @@ static void launch_bulk(K kernel, const StepArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(kernel, dim3(unsigned(a.bulk_grid)), dim3(256), 0, s, a);
 }
 
+// With ev, the bulk kernel is launched with start and stop events that its
+// dispatch itself stamps (hipExtLaunchKernelGGL), so the timed duration is the
+// kernel's alone, without the gaps around it.
 template <int ST, int COLL, int PAR>
-static void launch_bulk_t(const StepArgs &a, const StepArgs *pending, hipStream_t s) {
-    if (pending)
-        hipLaunchKernelGGL((k_excess_stream_collide<ST, COLL, PAR>), dim3(unsigned(EXCESS_WG + a.bulk_grid)),
-                           dim3(256), 0, s, a, *pending);
+static void launch_bulk_t(const StepArgs &a, const StepArgs *pending, hipStream_t s, const BulkEvents *ev) {
+    const dim3 fused(unsigned(EXCESS_WG + a.bulk_grid)), plain(unsigned(a.bulk_grid));
+    if (ev && pending)
+        hipExtLaunchKernelGGL((k_excess_stream_collide<ST, COLL, PAR>), fused, dim3(256), 0, s, ev->before,
+                              ev->after, 0, a, *pending);
+    else if (ev)
+        hipExtLaunchKernelGGL((k_stream_collide<ST, COLL, PAR>), plain, dim3(256), 0, s, ev->before, ev->after,
+                              0, a);
+    else if (pending)
+        hipLaunchKernelGGL((k_excess_stream_collide<ST, COLL, PAR>), fused, dim3(256), 0, s, a, *pending);
     else
         launch_bulk(k_stream_collide<ST, COLL, PAR>, a, s);
 }
@@ -1070,14 +1081,12 @@ static void launch_step_t(const StepArgs &a, int collision, int scheme, hipStrea
         hipLaunchKernelGGL(k_normals, dim3(lb), dim3(256), 0, s, a);
         hipLaunchKernelGGL(k_curvature, dim3(lb), dim3(256), 0, s, a);
     }
-    if (ev) (void)hipEventRecord(ev->before, s);
     // collision variant: bit 0 TRT, bit 1 Smagorinsky turbulence model, bit 2
     // free-slip walls
     const int coll = (collision ? 1 : 0) | (a.les_k > 0.0 ? 2 : 0) | (a.g.slip ? 4 : 0);
     launch_coll<ST>(coll, a.parity, [&](auto C, auto P) {
-        launch_bulk_t<ST, decltype(C)::value, decltype(P)::value>(a, pending, s);
+        launch_bulk_t<ST, decltype(C)::value, decltype(P)::value>(a, pending, s, ev);
     });
-    if (ev) (void)hipEventRecord(ev->after, s);
     launch_coll<ST>(coll, a.parity, [&](auto C, auto P) {
         hipLaunchKernelGGL((k_interface<ST, decltype(C)::value, decltype(P)::value>), dim3(lb), dim3(256), 0,
                            s, a);
