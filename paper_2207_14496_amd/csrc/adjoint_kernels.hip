@@ -259,54 +259,59 @@ __global__ __launch_bounds__(BS) void k_adj_refill(AdjArgs a) {
     const int b = blockIdx.y, n = blockIdx.x * BS + threadIdx.x;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     const long long gid = (long long)b * a.g.N + n;
-    if (n < a.g.N && a.s0.fl[gid] == F_GAS && a.s1.fl[gid] == F_IF) {
-        const Cell c = cell_of(a.g, b, n);
-        const long long cb = (long long)b * a.g.N;
-        const double *gr = a.grav + 3 * b;
-        int nv = 0;
-        double rs = 0.0, us[3] = {0.0, 0.0, 0.0};
-#pragma unroll 1
-        for (int i = 1; i < Q; ++i) {
-            const int q = nb_local(a.g, c.x, c.y, c.z, k_cx[i], k_cy[i], k_cz[i]);
-            if (!refill_source(a, cb, q)) continue;
-            double r, u[3];
-            moments1(a, b, q, gr, r, u);
-            ++nv;
-            rs += r;
-            for (int d = 0; d < 3; ++d) us[d] += u[d];
-        }
-        if (nv > 0) {
-            const double rb = rs / nv;
-            const double ub[3] = {us[0] / nv, us[1] / nv, us[2] / nv};
+    const bool mine = n < a.g.N && a.s0.fl[gid] == F_GAS && a.s1.fl[gid] == F_IF;
+    const long long cb = (long long)b * a.g.N;
+    const double *gr = a.grav + 3 * b;
+    const int lane = __lane_id();
+    // The wavefront's new cells one after the other, each by the whole
+    // wavefront: lane j in 1..18 takes the source x + c_j (its moments, and at
+    // the end its 19 adjoint contributions), lane i in 0..18 the refilled
+    // population i.  A cell's sources are then read in one round, not one
+    // after the other.
+    unsigned long long todo = __ballot(mine);
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        todo &= todo - 1;
+        const int cn = __shfl(n, leader);
+        const Cell c = cell_of(a.g, b, cn);
+        const bool has = lane >= 1 && lane < Q;
+        const int q = has ? nb_local(a.g, c.x, c.y, c.z, k_cx[lane], k_cy[lane], k_cz[lane]) : -1;
+        const bool valid = refill_source(a, cb, q);
+        double r = 1.0, u[3] = {0.0, 0.0, 0.0};
+        if (valid) moments1(a, b, q, gr, r, u);
+        const double nv = wave_sum(valid ? 1.0 : 0.0);
+        if (nv > 0.0) {
+            const double rb = wave_sum(valid ? r : 0.0) / nv;
+            const double ub[3] = {wave_sum(valid ? u[0] : 0.0) / nv, wave_sum(valid ? u[1] : 0.0) / nv,
+                                  wave_sum(valid ? u[2] : 0.0) / nv};
             const double uu = ub[0] * ub[0] + ub[1] * ub[1] + ub[2] * ub[2];
-            double lrb = 0.0, lub[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                const double l = a.lf1[pidx(a.g, b, i, n)];
-                const double uc = cx(i) * ub[0] + cy(i) * ub[1] + cz(i) * ub[2];
-                const double w = wgt<double>(i);
-                lrb += l * w * (1.0 + 3.0 * uc + 4.5 * uc * uc - 1.5 * uu);
-                const int ci[3] = {cx(i), cy(i), cz(i)};
-                for (int d = 0; d < 3; ++d) lub[d] += l * w * rb * (3.0 * ci[d] + 9.0 * uc * ci[d] - 3.0 * ub[d]);
+            // adjoint of the equilibrium refill f_i = f_eq_i(rho_bar, u_bar)
+            double pl = 0.0, pu[3] = {0.0, 0.0, 0.0};
+            if (lane < Q) {
+                const int ci[3] = {k_cx[lane], k_cy[lane], k_cz[lane]};
+                const double l = a.lf1[pidx(a.g, b, lane, cn)];
+                const double uc = ci[0] * ub[0] + ci[1] * ub[1] + ci[2] * ub[2];
+                const double w = lane == 0 ? 1.0 / 3.0 : (lane <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+                pl = l * w * (1.0 + 3.0 * uc + 4.5 * uc * uc - 1.5 * uu);
+                for (int d = 0; d < 3; ++d) pu[d] = l * w * rb * (3.0 * ci[d] + 9.0 * uc * ci[d] - 3.0 * ub[d]);
             }
+            const double lrb = wave_sum(pl);
+            const double lub[3] = {wave_sum(pu[0]), wave_sum(pu[1]), wave_sum(pu[2])};
             const double lr = lrb / nv;
             const double lu[3] = {lub[0] / nv, lub[1] / nv, lub[2] / nv};
             // rho(v) and u(v) = sum c f*(v) / rho(v) - g/2 of every source v
-#pragma unroll 1
-            for (int i = 1; i < Q; ++i) {
-                const int q = nb_local(a.g, c.x, c.y, c.z, k_cx[i], k_cy[i], k_cz[i]);
-                if (!refill_source(a, cb, q)) continue;
-                double r, u[3];
-                moments1(a, b, q, gr, r, u);
+            if (valid) {
+                const double ir = 1.0 / r;
 #pragma unroll
                 for (int k = 0; k < Q; ++k) {
                     const int ck[3] = {cx(k), cy(k), cz(k)};
                     double v = lr;
-                    for (int d = 0; d < 3; ++d) v += lu[d] * (ck[d] - (u[d] + 0.5 * gr[d])) / r;
+                    for (int d = 0; d < 3; ++d) v += lu[d] * (ck[d] - (u[d] + 0.5 * gr[d])) * ir;
                     atomicAdd(a.lf1 + pidx(a.g, b, k, q), v);
                 }
             }
-            for (int d = 0; d < 3; ++d) acc[1 + d] = -0.5 * lub[d];
+            if (lane == 0)
+                for (int d = 0; d < 3; ++d) acc[1 + d] += -0.5 * lub[d];
         }
     }
     block_add4(acc, a.gpart + ((long long)b * a.nblk + blockIdx.x) * 4);
