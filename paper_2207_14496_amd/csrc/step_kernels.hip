@@ -4,8 +4,8 @@
 // odd ones, see fslbm_device.hpp), five kernels plus three for surface tension:
 //   [sigma != 0]  k_band -> k_normals -> k_curvature    (Sec. 2.2, curvature)
 //   k_stream_collide  fluid tiles: liquid cells get the in-place stream +
-//                     bounce-back + collide; interface cells get their forced
-//                     filling/emptying class and are listed in tile order
+//                     bounce-back + collide; interface cells are listed in
+//                     tile order
 //   k_interface       interface list: the same update plus the mass exchange
 //                     (Sec. 2.2 mass flux with the forced filling/emptying
 //                     table), the anti-bounce-back condition, phi = m/rho and
@@ -15,10 +15,14 @@
 //                     marked cells: conversions, excess mass, receivers
 //                     (Sec. 2.2); from-liquid cells
 //   k_excess          receivers: gather excess shares (and the reservoir);
-//                     phi; bookkeeping for the next step
-// Only the bulk kernel touches every cell; the others walk compacted int32
-// lists whose lengths live in device memory, so the whole sequence can be
-// captured once and replayed as a HIP graph.
+//                     phi; forced filling/emptying classes of every interface
+//                     cell; bookkeeping for the next step
+// Inside a multi-step call a step's k_excess work runs in extra workgroups of
+// the next step's bulk kernel (k_excess_stream_collide); the call's last step
+// runs k_excess on its own.  Only the bulk kernel walks the domain (the tiles
+// that ever held fluid); the others walk compacted int32 lists whose lengths
+// live in device memory, so the whole sequence can be captured once and
+// replayed as a HIP graph.
 //
 // On MI355X every kernel boundary costs several microseconds (dispatch plus
 // the cross-XCD cache write-back and invalidate), which dominates these short
