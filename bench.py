@@ -168,7 +168,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py: this build runs on exactly one GPU (the path has no multi-GPU "
+        print("bench.py: this library runs on exactly one GPU (the path has no multi-GPU "
               "sharding); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
