@@ -49,7 +49,7 @@ class _Params(ctypes.Structure):
                 ("trt_lambda", ctypes.c_double), ("g", ctypes.c_double * 3),
                 ("sigma", ctypes.c_double), ("p_volume", ctypes.c_double),
                 ("eps_phi", ctypes.c_double), ("smag_cs", ctypes.c_double),
-                ("free_slip", ctypes.c_int)]
+                ("free_slip", ctypes.c_int), ("bubble_model", ctypes.c_int)]
 
 
 class Counts(ctypes.Structure):
@@ -74,8 +74,9 @@ def lib():
         _lib.orc_cell_omega.argtypes = [p_, p_, p_]
         _lib.orc_cell_omega.restype = d
         _lib.orc_normal.argtypes = [p_, p_, ctypes.c_long, p_]
-        _lib.orc_surface.argtypes = [p_, p_, p_, p_, p_]
-        _lib.orc_step.argtypes = [p_, p_, p_, p_, p_, p_, ctypes.c_int, p_]
+        _lib.orc_surface.argtypes = [p_, p_, p_, p_, p_, p_]
+        _lib.orc_step.argtypes = [p_, p_, p_, p_, p_, p_, p_, ctypes.c_int, p_]
+        _lib.orc_bubble_labels.argtypes = [p_, p_, p_]
         _lib.orc_init_equilibrium.argtypes = [p_, p_, p_, p_, p_]
         _lib.orc_total_mass.argtypes = [p_, p_, p_, p_, d]
         _lib.orc_total_mass.restype = d
@@ -104,6 +105,7 @@ class Params:
     eps_phi: float = 1e-2
     smag_cs: float = 0.0        # Smagorinsky constant C_S (0 = no turbulence model)
     free_slip: int = 0          # walls: 0 no-slip (bounce-back), 1 free-slip (specular)
+    bubble_model: int = 0       # 1: per-bubble volume pressures (reading R31)
 
     @property
     def N(self) -> int:
@@ -120,6 +122,7 @@ class Params:
         p.sigma, p.p_volume, p.eps_phi = float(self.sigma), float(self.p_volume), float(self.eps_phi)
         p.smag_cs = float(self.smag_cs)
         p.free_slip = int(self.free_slip)
+        p.bubble_model = int(self.bubble_model)
         return p
 
 
@@ -131,10 +134,12 @@ class State:
     phi: np.ndarray
     reservoir: float = 0.0
     counts: dict = field(default_factory=dict)
+    pbub: np.ndarray = None     # bubble pressure per gas / interface cell (bubble model)
 
     def copy(self) -> "State":
         return State(self.flags.copy(), self.f.copy(), self.m.copy(), self.phi.copy(),
-                     self.reservoir, dict(self.counts))
+                     self.reservoir, dict(self.counts),
+                     None if self.pbub is None else self.pbub.copy())
 
 
 def _ptr(a: np.ndarray):
@@ -189,7 +194,7 @@ def surface(params: Params, flags: np.ndarray, phi: np.ndarray):
     kappa = np.zeros(params.N)
     p = params.c()
     lib().orc_surface(ctypes.byref(p), _ptr(np.ascontiguousarray(flags, np.uint8)),
-                      _ptr(np.ascontiguousarray(phi, np.float64)), _ptr(rhoG), _ptr(kappa))
+                      _ptr(np.ascontiguousarray(phi, np.float64)), None, _ptr(rhoG), _ptr(kappa))
     return rhoG, kappa
 
 
@@ -207,7 +212,20 @@ def init_state(params: Params, flags, phi, rho, u, mass=None) -> State:
         m = np.where(flags == INTERFACE, phi * rho, 0.0)
     else:
         m = np.where(flags == INTERFACE, np.asarray(mass, np.float64).reshape(N), 0.0)
-    return State(flags, f, np.ascontiguousarray(m), phi)
+    pbub = None
+    if params.bubble_model:
+        # every bubble starts at the volume pressure p_V(0)
+        pbub = np.where(flags != LIQUID, float(params.p_volume), 0.0)
+    return State(flags, f, np.ascontiguousarray(m), phi, pbub=pbub)
+
+
+def bubble_labels(params: Params, flags) -> np.ndarray:
+    """Bubble label of every cell (smallest cell index of its connected set of
+    gas and interface cells; -1 on liquid cells), reading R31."""
+    lab = np.zeros(params.N, dtype=np.int64)
+    p = params.c()
+    lib().orc_bubble_labels(ctypes.byref(p), _ptr(np.ascontiguousarray(flags, np.uint8)), _ptr(lab))
+    return lab
 
 
 def step(params: Params, st: State, nsteps: int = 1) -> State:
@@ -215,8 +233,11 @@ def step(params: Params, st: State, nsteps: int = 1) -> State:
     p = params.c()
     res = ctypes.c_double(st.reservoir)
     cnt = Counts()
+    if params.bubble_model and st.pbub is None:
+        raise ValueError("the bubble model needs the state's bubble pressures (init_state)")
+    pb = _ptr(st.pbub) if params.bubble_model else None
     lib().orc_step(ctypes.byref(p), _ptr(st.flags), _ptr(st.f), _ptr(st.m), _ptr(st.phi),
-                   ctypes.byref(res), int(nsteps), ctypes.byref(cnt))
+                   ctypes.byref(res), pb, int(nsteps), ctypes.byref(cnt))
     st.reservoir = res.value
     st.counts = cnt.as_dict()
     return st

@@ -74,6 +74,20 @@
  *       there is rebuilt by anti-bounce-back like any gas source.  Classes,
  *       conflicts, refill sources, excess receivers and normals keep treating
  *       walls as no cells.
+ *   R31 bubble model (Sec. 2.2, volume pressure p_V(t) = p_V(0) V(0)/V(t) of
+ *       an enclosed gas volume, tracked through coalescence and segmentation):
+ *       a bubble is a connected set of gas and interface cells (D3Q19 links,
+ *       as R8); a cell holds the gas volume max(0, 1 - phi), a bubble V = the
+ *       sum over its cells.  A set that holds a cell of the top layer
+ *       (z = nz-1) is the atmosphere and keeps p_V(0).  Every other bubble
+ *       carries an amount n = p V: at the end of a step, each bubble b of the
+ *       step's start hands its amount p_b V_b to the bubbles of the step's
+ *       end, shared by the gas volume of its cells that each of them holds, and
+ *       p_k = n_k / V_k.  So a bubble without a topology change keeps p V
+ *       (Boyle's law), a merge adds amounts, and the parts of a split share
+ *       one pressure.  The free-surface condition uses
+ *       rho_G = 3 (p_k + 2 sigma kappa_m) with the pressure of the cell's
+ *       bubble.
  */
 #include <math.h>
 #include <stdint.h>
@@ -108,6 +122,7 @@ typedef struct {
     double eps_phi;    /* conversion threshold */
     double smag_cs;    /* Smagorinsky constant C_S (0 = no turbulence model) */
     int free_slip;     /* walls: 0 no-slip (bounce-back), 1 free-slip (specular) */
+    int bubble_model;  /* 0 one volume pressure p_V; 1 per-bubble pressures (R31) */
 } orc_params;
 
 /* Per-step counters that the tests use to check the conversion logic. */
@@ -379,11 +394,11 @@ void orc_normal(const orc_params *p, const double *phi, long n, double out[3])
  * density rho_G = 3 (p_V + 2 sigma kappa_m).  kappa may be NULL.
  */
 void orc_surface(const orc_params *p, const uint8_t *flag, const double *phi,
-                 double *rhoG, double *kappa)
+                 const double *pvol, double *rhoG, double *kappa)
 {
     long N = (long)p->nx * p->ny * p->nz;
     for (long n = 0; n < N; ++n) {
-        rhoG[n] = 3.0 * p->p_volume;
+        rhoG[n] = 3.0 * (pvol ? pvol[n] : p->p_volume);
         if (kappa) kappa[n] = 0.0;
     }
     if (N <= 0 || (p->sigma == 0.0 && !kappa)) return;
@@ -415,7 +430,7 @@ void orc_surface(const orc_params *p, const uint8_t *flag, const double *phi,
         }
         double km = -0.5 * div;
         if (kappa) kappa[n] = km;
-        rhoG[n] = 3.0 * (p->p_volume + 2.0 * p->sigma * km);
+        rhoG[n] = 3.0 * ((pvol ? pvol[n] : p->p_volume) + 2.0 * p->sigma * km);
     }
     free(nh);
     free(band);
@@ -599,11 +614,77 @@ void orc_stream_cell(const orc_params *p, const uint8_t *flag, const double *fs,
     stream_cell(p, flag, fs, rhoG, N, n, fn);
 }
 
+/* Gas volume of a cell (R31). */
+static double gas_volume(double phi) { return phi < 1.0 ? 1.0 - phi : 0.0; }
+
+/* Bubbles (R31): the connected sets of gas and interface cells over D3Q19
+ * links, each labelled with its smallest cell index (breadth-first from the
+ * lowest unlabelled cell); liquid cells get -1. */
+static void bubble_labels(const orc_params *p, const uint8_t *flag, long *lab)
+{
+    long N = (long)p->nx * p->ny * p->nz;
+    long *queue = malloc(sizeof(long) * (N > 0 ? N : 1));
+    for (long n = 0; n < N; ++n) lab[n] = -1;
+    for (long s0 = 0; s0 < N; ++s0) {
+        if (flag[s0] == LIQ || lab[s0] >= 0) continue;
+        long head = 0, tail = 0;
+        queue[tail++] = s0;
+        lab[s0] = s0;
+        while (head < tail) {
+            long n = queue[head++];
+            for (int i = 1; i < Q; ++i) {
+                long k = nb19(p, n, i);
+                if (k < 0 || flag[k] == LIQ || lab[k] >= 0) continue;
+                lab[k] = s0;
+                queue[tail++] = k;
+            }
+        }
+    }
+    free(queue);
+}
+
+/* The bubble pressures after a step (R31).  lab0 / V0: the bubbles of the
+ * step's start and their volumes; pbub holds the pressures of the start on
+ * entry and of the end on return (0 on liquid cells). */
+static void bubble_update(const orc_params *p, const uint8_t *flag, const double *phi,
+                          const long *lab0, const double *V0, double *pbub)
+{
+    long N = (long)p->nx * p->ny * p->nz, layer = (long)p->nx * p->ny;
+    long *lab1 = malloc(sizeof(long) * (N > 0 ? N : 1));
+    double *V1 = calloc((size_t)N + 1, sizeof(double)), *amount = calloc((size_t)N + 1, sizeof(double));
+    double *kept = calloc((size_t)N + 1, sizeof(double));
+    uint8_t *atm = calloc((size_t)N + 1, 1);
+    bubble_labels(p, flag, lab1);
+    for (long n = 0; n < N; ++n) {
+        if (lab1[n] < 0) continue;
+        V1[lab1[n]] += gas_volume(phi[n]);
+        if (n / layer == p->nz - 1) atm[lab1[n]] = 1;
+    }
+    /* each old bubble's amount, shared by the gas volume of its cells that
+     * are still gas or interface */
+    for (long n = 0; n < N; ++n)
+        if (lab0[n] >= 0 && lab1[n] >= 0) kept[lab0[n]] += gas_volume(phi[n]);
+    for (long n = 0; n < N; ++n) {
+        if (lab0[n] < 0 || lab1[n] < 0) continue;
+        long b = lab0[n];
+        if (kept[b] > 0.0) amount[lab1[n]] += pbub[b] * V0[b] * gas_volume(phi[n]) / kept[b];
+    }
+    for (long n = 0; n < N; ++n) {
+        long k = lab1[n];
+        if (k < 0) pbub[n] = 0.0;
+        else if (atm[k] || !(V1[k] > 0.0) || !(amount[k] > 0.0)) pbub[n] = p->p_volume;
+        else pbub[n] = amount[k] / V1[k];
+    }
+    free(lab1); free(V1); free(amount); free(kept); free(atm);
+}
+
 /*
- * One FSLBM time step on the canonical state (in place).  Returns 0.
+ * One FSLBM time step on the canonical state (in place).  pbub: the bubble
+ * pressure of every gas and interface cell (R31), or NULL without the bubble
+ * model.  Returns 0.
  */
 static int step_once(const orc_params *p, uint8_t *flag, double *f, double *m, double *phi,
-                     double *reservoir, orc_counts *cnt)
+                     double *reservoir, double *pbub, orc_counts *cnt)
 {
     long N = (long)p->nx * p->ny * p->nz;
     double *fs = malloc(sizeof(double) * Q * N); /* f*(t) */
@@ -617,8 +698,20 @@ static int step_once(const orc_params *p, uint8_t *flag, double *f, double *m, d
     memcpy(fs, f, sizeof(double) * Q * N);
     memcpy(phis, phi, sizeof(double) * N);
 
+    /* the bubbles at the step's start and their volumes (R31) */
+    const int bubbles = p->bubble_model && pbub;
+    long *lab0 = NULL;
+    double *V0 = NULL;
+    if (bubbles) {
+        lab0 = malloc(sizeof(long) * (N > 0 ? N : 1));
+        V0 = calloc((size_t)N + 1, sizeof(double));
+        bubble_labels(p, flag, lab0);
+        for (long n = 0; n < N; ++n)
+            if (lab0[n] >= 0) V0[lab0[n]] += gas_volume(phi[n]);
+    }
+
     /* S0: surface geometry from phi(t). */
-    orc_surface(p, flag, phi, rhoG, NULL);
+    orc_surface(p, flag, phi, bubbles ? pbub : NULL, rhoG, NULL);
 
     /* Thuerey classes of interface cells from flags(t). */
     for (long n = 0; n < N; ++n)
@@ -748,18 +841,29 @@ static int step_once(const orc_params *p, uint8_t *flag, double *f, double *m, d
     for (long n = 0; n < N; ++n)
         if (touched[n]) phi[n] = m[n] / rho_post(f, N, n);
 
+    if (bubbles) {
+        bubble_update(p, flag, phi, lab0, V0, pbub);
+        free(lab0); free(V0);
+    }
     free(fs); free(rhoG); free(cls); free(toliq); free(togas); free(newg); free(froml);
     free(conv); free(touched); free(mex); free(phis);
     return 0;
 }
 
 int orc_step(const orc_params *p, uint8_t *flag, double *f, double *m, double *phi,
-             double *reservoir, int nsteps, orc_counts *cnt)
+             double *reservoir, double *pbub, int nsteps, orc_counts *cnt)
 {
     if (cnt) memset(cnt, 0, sizeof(*cnt));
     nb_table(p);
-    for (int s = 0; s < nsteps; ++s) step_once(p, flag, f, m, phi, reservoir, cnt);
+    for (int s = 0; s < nsteps; ++s) step_once(p, flag, f, m, phi, reservoir, pbub, cnt);
     return 0;
+}
+
+/* Bubble labels of a state (R31), for the tests. */
+void orc_bubble_labels(const orc_params *p, const uint8_t *flag, long *lab)
+{
+    nb_table(p);
+    bubble_labels(p, flag, lab);
 }
 
 /* Equilibrium initial PDFs f* = f_eq(rho, u) of liquid and interface cells;

@@ -268,6 +268,26 @@ def drop_impact(n=256, pool_depth=64, radius=16.0, drop_centre_z=104.0, drop_u=0
     return _finish(s, phi3, rho3)
 
 
+def rising_bubbles(nx=24, ny=8, nz=40, centres=((12.0, 4.0, 10.0),), radius=4.0, omega=1.7,
+                   g=1e-4, refill=0, name="rising-bubbles") -> Setup:
+    """Gas bubbles (spheres of the given radius) in a liquid-filled box: periodic
+    x and y, walls in z, gravity -g along z, TRT, hydrostatic density.  No gas
+    reaches the top layer, so with the bubble model every bubble is enclosed."""
+    s = Setup(name, nx, ny, nz, (1, 1, 0), 1, omega, (0.0, 0.0, -g), refill=refill)
+
+    def sd(x, y, z):
+        d = np.full(np.broadcast(x, y, z).shape, np.inf)
+        for cx, cy, cz in centres:
+            d = np.minimum(d, np.sqrt((x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2) - radius)
+        return -d   # negative (liquid) outside every sphere
+
+    phi3 = shape_fill(nx, ny, nz, sd)
+    zc = np.broadcast_to(_centres(nz)[:, None, None], (nz, ny, nx))
+    rho3 = 1.0 + 3.0 * g * (nz - zc)
+    s.meta = dict(centres=tuple(centres), radius=radius)
+    return _finish(s, phi3, rho3)
+
+
 def cyl_dam_break(nx=512, ny=512, nz=96, radius=64.0, height=80.0, omega=1.9, g=2e-5,
                   refill=0, name="cyl-dam-break") -> Setup:
     """Cylindrical dam break: liquid cylinder (axis z) of radius r and height h at
