@@ -96,7 +96,8 @@ enum {
     FSLBM_FIELD_MASS = 1u << 2,
     FSLBM_FIELD_PHI = 1u << 3,
     FSLBM_FIELD_RHO = 1u << 4,
-    FSLBM_FIELD_VEL = 1u << 5
+    FSLBM_FIELD_VEL = 1u << 5,
+    FSLBM_FIELD_BUBBLE_PRESSURE = 1u << 6   /* [B][N] f64, bubble_model = 1 only */
 };
 
 typedef struct fslbm_params {
@@ -130,6 +131,20 @@ typedef struct fslbm_params {
                              * velocity components reversed, in the cell shifted
                              * by the other components; the mass exchange follows
                              * the same path)                                        */
+    int32_t bubble_model;   /* volume pressure (Sec. 2.2, p_V(t) = p_V(0) V(0)/V(t)
+                             * of an enclosed gas volume): 0 the one constant
+                             * p_volume; 1 per bubble.  A bubble is a connected
+                             * set of gas and interface cells (D3Q19 links); a
+                             * cell holds the gas volume max(0, 1 - phi).  A set
+                             * that reaches the top layer (z = nz-1) is the
+                             * atmosphere at p_volume; every other bubble carries
+                             * the amount p V, handed on at each step to the
+                             * bubbles that hold its cells (shared by their gas
+                             * volume), so p V is kept, merges add, splits share
+                             * one pressure.  Every bubble starts at p_volume.
+                             * Steps run without graphs and without the fused
+                             * excess work; fslbm_step_timed and the reverse mode
+                             * reject it.                                          */
 } fslbm_params;
 
 typedef struct fslbm_ctx fslbm_ctx;

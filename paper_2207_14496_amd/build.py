@@ -26,6 +26,7 @@ UNITS = [
     ("step_kernels.hip", ["-DFSLBM_UNIT_DISPATCH=1"]),
     ("adjoint_kernels.hip", []),
     ("adjoint_api.hip", []),
+    ("bubble.hip", []),
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -41,6 +41,7 @@ const char *check_config(const fslbm_ctx *c) {
     if (p.sigma != 0.0) return "the adjoint needs sigma = 0";
     if (p.smagorinsky_cs != 0.0) return "the adjoint needs smagorinsky_cs = 0";
     if (p.free_slip != 0) return "the adjoint needs no-slip walls";
+    if (p.bubble_model != 0) return "the adjoint needs the constant volume pressure (bubble_model = 0)";
     if (p.refill != FSLBM_REFILL_EQ) return "the adjoint needs EQ refilling";
     if (p.batch > 65535) return "the adjoint supports at most 65535 domains";
     return nullptr;

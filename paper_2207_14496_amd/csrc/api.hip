@@ -61,6 +61,16 @@ bool make_layout(const fslbm_params &p, Layout &L) {
     const size_t ntiles = size_t(tile_count(BN));
     L.tiles = take(ntiles * 4);
     L.tile_bits = take((ntiles + 31) / 32 * 4);
+    const bool bub = p.bubble_model != 0;
+    L.pbub = bub ? take(size_t(BN) * 8) : 0;
+    L.blab0 = bub ? take(size_t(BN) * 4) : 0;
+    L.blab1 = bub ? take(size_t(BN) * 4) : 0;
+    L.bV0 = bub ? take(size_t(BN) * 8) : 0;
+    L.bV1 = bub ? take(size_t(BN) * 8) : 0;
+    L.bkept = bub ? take(size_t(BN) * 8) : 0;
+    L.bamount = bub ? take(size_t(BN) * 8) : 0;
+    L.batm = bub ? take(size_t(BN) * 4) : 0;
+    L.bflag = bub ? take(256) : 0;
     L.total = off;
     return true;
 }
@@ -79,6 +89,7 @@ const char *validate(const fslbm_params *p) {
     if (!(p->eps_phi >= 0.0)) return "eps_phi must be >= 0";
     if (!(p->smagorinsky_cs >= 0.0) || !(p->smagorinsky_cs < 1e3)) return "smagorinsky_cs must be finite and >= 0";
     if (p->free_slip != 0 && p->free_slip != 1) return "free_slip must be 0 or 1";
+    if (p->bubble_model != 0 && p->bubble_model != 1) return "bubble_model must be 0 or 1";
     if (p->omega_b)
         for (int b = 0; b < p->batch; ++b)
             if (!(p->omega_b[b] > 0.0 && p->omega_b[b] < 2.0)) return "omega_b must lie in (0, 2)";
@@ -357,6 +368,7 @@ StepArgs make_args(fslbm_ctx *c, int parity) {
     a.rho_if = at<double>(c, c->L.rho_if);
     bool surf = p.sigma != 0.0;
     a.rhoG = surf ? at<double>(c, c->L.rhoG) : nullptr;
+    a.pbub = p.bubble_model ? at<double>(c, c->L.pbub) : nullptr;
     a.normal = surf ? at<double>(c, c->L.normal) : nullptr;
     a.band = surf ? at<uint32_t>(c, c->L.band) : nullptr;
     a.omega = at<double>(c, c->L.omega);
@@ -519,7 +531,8 @@ bool load_state(fslbm_ctx *c, const uint8_t *flags, const double *phi, const dou
     hipLaunchKernelGGL(k_init_lists, dim3(nblk), dim3(256), 0, c->stream, a);
     if (!hip_ok(c, hipGetLastError(), "k_init_lists")) return false;
     hipLaunchKernelGGL(k_init_tiles, dim3(nblk), dim3(256), 0, c->stream, a);
-    return hip_ok(c, hipGetLastError(), "k_init_tiles");
+    if (!hip_ok(c, hipGetLastError(), "k_init_tiles")) return false;
+    return !c->p.bubble_model || bubble_reset(c);
 }
 
 bool refresh_bulk_grid(fslbm_ctx *c) {
@@ -628,6 +641,20 @@ fslbm_status fslbm_step(fslbm_ctx *c, int32_t nsteps) {
     if (!c) return FSLBM_EINVAL;
     if (c->status != FSLBM_OK) return c->status;
     if (nsteps < 0) return fail(c, FSLBM_EINVAL, "nsteps must be >= 0");
+    if (c->p.bubble_model) {
+        // the bubbles of the step's start, the step with direct launches and
+        // its own excess work, then the bubble pressures of its end
+        for (int32_t s = 0; s < nsteps; ++s) {
+            if (!bubble_begin(c)) return c->status;
+            launch_step(make_args(c, int(c->t & 1)), c->p.storage, c->p.collision, c->p.refill, c->stream,
+                        nullptr, nullptr, true);
+            if (!hip_ok(c, hipGetLastError(), "step kernel launch")) return c->status;
+            c->pending = false;
+            ++c->t;
+            if (!bubble_end(c)) return c->status;
+        }
+        return FSLBM_OK;
+    }
     // each step's excess-mass redistribution runs inside the next step's bulk
     // kernel; the last step finishes its own
     for (int32_t s = 0; s < nsteps; ++s)
@@ -639,6 +666,7 @@ fslbm_status fslbm_step_timed(fslbm_ctx *c, int32_t nsteps, double *bulk_ms, dou
     if (!c) return FSLBM_EINVAL;
     if (c->status != FSLBM_OK) return c->status;
     if (nsteps < 1 || !bulk_ms || !total_ms) return fail(c, FSLBM_EINVAL, "nsteps >= 1 and outputs required");
+    if (c->p.bubble_model) return fail(c, FSLBM_EINVAL, "fslbm_step_timed does not run the bubble model");
     std::vector<hipEvent_t> ev(size_t(2) * nsteps + 2, nullptr);
     bool ok = true;
     for (auto &e : ev)
@@ -708,11 +736,18 @@ fslbm_status fslbm_set_stream(fslbm_ctx *c, void *stream) {
 fslbm_status fslbm_read_fields(fslbm_ctx *c, uint32_t mask, void *const *dst) {
     if (!c) return FSLBM_EINVAL;
     if (c->status != FSLBM_OK) return c->status;
-    if (mask & ~0x3Fu) return fail(c, FSLBM_EINVAL, "unknown field bits");
+    if (mask & ~0x7Fu) return fail(c, FSLBM_EINVAL, "unknown field bits");
     if (!dst && mask) return fail(c, FSLBM_EINVAL, "dst is NULL");
-    for (int k = 0; k < 6; ++k)
+    for (int k = 0; k < 7; ++k)
         if ((mask >> k & 1u) && !dst[k]) return fail(c, FSLBM_EINVAL, "NULL destination for a requested field");
-    if (!enqueue_read(c, mask, dst)) return c->status;
+    if ((mask & FSLBM_FIELD_BUBBLE_PRESSURE) && !c->p.bubble_model)
+        return fail(c, FSLBM_EINVAL, "the bubble pressure needs bubble_model = 1");
+    if (!enqueue_read(c, mask & 0x3Fu, dst)) return c->status;
+    if ((mask & FSLBM_FIELD_BUBBLE_PRESSURE) &&
+        !hip_ok(c, hipMemcpyAsync(dst[6], at<double>(c, c->L.pbub),
+                                  size_t(c->p.nx) * c->p.ny * c->p.nz * c->p.batch * 8,
+                                  hipMemcpyDeviceToDevice, c->stream), "hipMemcpy(bubble pressure)"))
+        return c->status;
     if (!hip_ok(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize")) return c->status;
     if (!device_errors_ok(c) || !refresh_bulk_grid(c)) return c->status;
     return FSLBM_OK;

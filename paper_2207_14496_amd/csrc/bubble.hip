@@ -1,0 +1,181 @@
+// bubble.hip -- the bubble model (Sec. 2.2: the volume pressure of an
+// enclosed gas volume, p_V(t) = p_V(0) V(0) / V(t), tracked through
+// coalescence and segmentation).
+//
+// A bubble is a connected set of gas and interface cells over D3Q19 links; a
+// cell holds the gas volume max(0, 1 - phi) and a bubble V, the sum over its
+// cells.  A set that reaches the top layer (z = nz - 1) is the atmosphere and
+// stays at p_volume.  Every other bubble carries the amount p V.  At the end
+// of a step each bubble b of the step's start hands p_b V_b to the bubbles of
+// the step's end, shared by the gas volume of b's cells that each of them
+// holds, and p_k = n_k / V_k: a bubble without a topology change keeps p V
+// (Boyle's law), a merge adds amounts, the parts of a split share one pressure.
+//
+// Labels are global cell indices: every set ends up labelled with its
+// smallest cell index.  They come from passes of label propagation (each cell
+// takes the smallest label around it, then the label of the cell its label
+// names) until a pass changes nothing; the host reads the change flag after
+// each pass.  Per-label sums are double atomics.  The model runs with direct
+// launches between the steps (fslbm_step), for the runs with enclosed gas.
+#include "context.hpp"
+
+namespace fslbm {
+namespace {
+
+constexpr int BS = 256;
+
+__device__ __forceinline__ bool gas_phase(uint8_t f) { return (f & (F_IF | F_GAS)) != 0; }
+__device__ __forceinline__ double gas_volume(double phi) { return phi < 1.0 ? 1.0 - phi : 0.0; }
+
+// Every gas and interface cell labelled with its own index, liquid -1.
+__global__ __launch_bounds__(BS) void k_bub_seed(StepArgs a, int32_t *lab) {
+    const long long gid = (long long)blockIdx.x * BS + threadIdx.x;
+    if (gid >= a.g.BN) return;
+    lab[gid] = gas_phase(a.flags[gid]) ? int32_t(gid) : -1;
+}
+
+// One propagation pass.  Labels only ever name gas or interface cells of the
+// same set and only fall, so the fixed point is each set's smallest index.
+__global__ __launch_bounds__(BS) void k_bub_pass(StepArgs a, int32_t *lab, int32_t *changed) {
+    const long long gid = (long long)blockIdx.x * BS + threadIdx.x;
+    if (gid >= a.g.BN) return;
+    const int32_t l0 = lab[gid];
+    if (l0 < 0) return;
+    const Cell c = decode(a.g, gid);
+    const long long cb = (long long)c.b * a.g.N;
+    int32_t m = l0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const int q = nb_local(a.g, c.x, c.y, c.z, cx(i), cy(i), cz(i));
+        const int32_t lq = q >= 0 ? lab[cb + q] : -1;
+        m = (lq >= 0 && lq < m) ? lq : m;
+    }
+    const int32_t mm = lab[m];   // the label of the cell m (a gas or interface cell)
+    m = (mm >= 0 && mm < m) ? mm : m;
+    if (m < l0) {
+        lab[gid] = m;
+        *changed = 1;
+    }
+}
+
+// Gas volume per label; with top, the labels that reach the top layer.
+__global__ __launch_bounds__(BS) void k_bub_volume(StepArgs a, const int32_t *lab, const double *phi,
+                                                   double *V, int32_t *atm) {
+    const long long gid = (long long)blockIdx.x * BS + threadIdx.x;
+    if (gid >= a.g.BN) return;
+    const int32_t l = lab[gid];
+    if (l < 0) return;
+    atomicAdd(V + l, gas_volume(phi[gid]));
+    if (atm && decode(a.g, gid).z == a.g.nz - 1) atm[l] = 1;
+}
+
+// Gas volume of every start bubble's cells that are still gas or interface.
+__global__ __launch_bounds__(BS) void k_bub_kept(StepArgs a, const int32_t *lab0, const int32_t *lab1,
+                                                 const double *phi, double *kept) {
+    const long long gid = (long long)blockIdx.x * BS + threadIdx.x;
+    if (gid >= a.g.BN) return;
+    const int32_t b = lab0[gid];
+    if (b < 0 || lab1[gid] < 0) return;
+    atomicAdd(kept + b, gas_volume(phi[gid]));
+}
+
+// Each start bubble's amount p V, handed to the end bubbles by gas volume.
+__global__ __launch_bounds__(BS) void k_bub_amount(StepArgs a, const int32_t *lab0, const int32_t *lab1,
+                                                   const double *phi, const double *pbub, const double *V0,
+                                                   const double *kept, double *amount) {
+    const long long gid = (long long)blockIdx.x * BS + threadIdx.x;
+    if (gid >= a.g.BN) return;
+    const int32_t b = lab0[gid], k = lab1[gid];
+    if (b < 0 || k < 0 || !(kept[b] > 0.0)) return;
+    atomicAdd(amount + k, pbub[b] * V0[b] * gas_volume(phi[gid]) / kept[b]);
+}
+
+// The pressures of the end bubbles (0 on liquid cells).
+__global__ __launch_bounds__(BS) void k_bub_assign(StepArgs a, const int32_t *lab1, const double *V1,
+                                                   const double *amount, const int32_t *atm, double *pbub) {
+    const long long gid = (long long)blockIdx.x * BS + threadIdx.x;
+    if (gid >= a.g.BN) return;
+    const int32_t k = lab1[gid];
+    double p = 0.0;
+    if (k >= 0) p = (atm[k] || !(V1[k] > 0.0) || !(amount[k] > 0.0)) ? a.p_volume : amount[k] / V1[k];
+    pbub[gid] = p;
+}
+
+__global__ __launch_bounds__(BS) void k_bub_reset(StepArgs a, double *pbub) {
+    const long long gid = (long long)blockIdx.x * BS + threadIdx.x;
+    if (gid >= a.g.BN) return;
+    pbub[gid] = gas_phase(a.flags[gid]) ? a.p_volume : 0.0;
+}
+
+unsigned blocks(const StepArgs &a) { return unsigned((a.g.BN + BS - 1) / BS); }
+
+// Label the gas and interface sets of the current flags into lab.
+bool label(fslbm_ctx *c, const StepArgs &a, int32_t *lab) {
+    int32_t *flag = at<int32_t>(c, c->L.bflag);
+    hipLaunchKernelGGL(k_bub_seed, dim3(blocks(a)), dim3(BS), 0, c->stream, a, lab);
+    if (!hip_ok(c, hipGetLastError(), "k_bub_seed")) return false;
+    // each pass lowers at least one label while any is not final
+    const long long cap = 8LL * (c->p.nx + c->p.ny + c->p.nz) + 1024;
+    for (long long it = 0; it < cap; ++it) {
+        int32_t h = 0;
+        if (!hip_ok(c, hipMemsetAsync(flag, 0, 4, c->stream), "hipMemset(bubble flag)")) return false;
+        hipLaunchKernelGGL(k_bub_pass, dim3(blocks(a)), dim3(BS), 0, c->stream, a, lab, flag);
+        if (!hip_ok(c, hipGetLastError(), "k_bub_pass") ||
+            !hip_ok(c, hipMemcpyAsync(&h, flag, 4, hipMemcpyDeviceToHost, c->stream), "hipMemcpy(bubble flag)") ||
+            !hip_ok(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize"))
+            return false;
+        if (!h) return true;
+    }
+    fail(c, FSLBM_EDEVICE, "bubble labels did not settle");
+    return false;
+}
+
+}  // namespace
+
+bool bubble_begin(fslbm_ctx *c) {
+    const StepArgs a = make_args(c, int(c->t & 1));
+    const size_t BN = size_t(a.g.BN);
+    int32_t *lab0 = at<int32_t>(c, c->L.blab0);
+    double *V0 = at<double>(c, c->L.bV0);
+    if (!label(c, a, lab0)) return false;
+    if (!hip_ok(c, hipMemsetAsync(V0, 0, BN * 8, c->stream), "hipMemset(bubble volumes)")) return false;
+    hipLaunchKernelGGL(k_bub_volume, dim3(blocks(a)), dim3(BS), 0, c->stream, a, lab0, a.phi_cur, V0,
+                       static_cast<int32_t *>(nullptr));
+    return hip_ok(c, hipGetLastError(), "k_bub_volume");
+}
+
+bool bubble_end(fslbm_ctx *c) {
+    // after the step: phi_cur of the next step's arguments is the step's result
+    const StepArgs a = make_args(c, int(c->t & 1));
+    const size_t BN = size_t(a.g.BN);
+    int32_t *lab0 = at<int32_t>(c, c->L.blab0), *lab1 = at<int32_t>(c, c->L.blab1);
+    int32_t *atm = at<int32_t>(c, c->L.batm);
+    double *V0 = at<double>(c, c->L.bV0), *V1 = at<double>(c, c->L.bV1);
+    double *kept = at<double>(c, c->L.bkept), *amount = at<double>(c, c->L.bamount);
+    double *pbub = at<double>(c, c->L.pbub);
+    if (!label(c, a, lab1)) return false;
+    bool ok = hip_ok(c, hipMemsetAsync(V1, 0, BN * 8, c->stream), "hipMemset") &&
+              hip_ok(c, hipMemsetAsync(kept, 0, BN * 8, c->stream), "hipMemset") &&
+              hip_ok(c, hipMemsetAsync(amount, 0, BN * 8, c->stream), "hipMemset") &&
+              hip_ok(c, hipMemsetAsync(atm, 0, BN * 4, c->stream), "hipMemset");
+    if (!ok) return false;
+    const unsigned nb = blocks(a);
+    hipLaunchKernelGGL(k_bub_volume, dim3(nb), dim3(BS), 0, c->stream, a, lab1, a.phi_cur, V1, atm);
+    hipLaunchKernelGGL(k_bub_kept, dim3(nb), dim3(BS), 0, c->stream, a, lab0, lab1, a.phi_cur, kept);
+    hipLaunchKernelGGL(k_bub_amount, dim3(nb), dim3(BS), 0, c->stream, a, lab0, lab1, a.phi_cur,
+                       static_cast<const double *>(pbub), static_cast<const double *>(V0),
+                       static_cast<const double *>(kept), amount);
+    hipLaunchKernelGGL(k_bub_assign, dim3(nb), dim3(BS), 0, c->stream, a, lab1, static_cast<const double *>(V1),
+                       static_cast<const double *>(amount), static_cast<const int32_t *>(atm), pbub);
+    if (!hip_ok(c, hipGetLastError(), "bubble kernels")) return false;
+    // the refills may have opened tiles: keep the bulk grid large enough
+    return refresh_bulk_grid(c);
+}
+
+bool bubble_reset(fslbm_ctx *c) {
+    const StepArgs a = make_args(c, int(c->t & 1));
+    hipLaunchKernelGGL(k_bub_reset, dim3(blocks(a)), dim3(BS), 0, c->stream, a, at<double>(c, c->L.pbub));
+    return hip_ok(c, hipGetLastError(), "k_bub_reset");
+}
+
+}  // namespace fslbm

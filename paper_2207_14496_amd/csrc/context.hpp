@@ -23,6 +23,9 @@ struct Layout {
     size_t claim;
     size_t cnt, nif, res, omega, grav, diag_d, diag_i;
     size_t tiles, tile_bits;
+    // bubble model: per-cell pressure (the state), labels at the step's start
+    // and end, per-label sums, the label pass's change flag
+    size_t pbub, blab0, blab1, bV0, bV1, bkept, bamount, batm, bflag;
     size_t total;
 };
 
@@ -87,5 +90,12 @@ bool refresh_bulk_grid(fslbm_ctx *c);
 
 // Enqueue the canonical read-back of the fields in `mask` (no synchronisation).
 bool enqueue_read(fslbm_ctx *c, uint32_t mask, void *const *dst);
+
+// Bubble model (bubble_model = 1): the bubbles and their volumes at the start
+// of a step, and their pressures at its end.  Both synchronise the stream.
+bool bubble_begin(fslbm_ctx *c);
+bool bubble_end(fslbm_ctx *c);
+// Every gas and interface cell at p_volume (after a state is loaded).
+bool bubble_reset(fslbm_ctx *c);
 
 }  // namespace fslbm

@@ -268,6 +268,8 @@ struct StepArgs {
     double *phi_cur;       // [BN] fill level at the start of this step
     double *phi_next;      // [BN] fill level at the end of this step (the other buffer)
     double *rhoG;          // [BN] gas density at interface cells (sigma != 0), else null
+    const double *pbub;    // [BN] bubble pressure of every gas and interface cell (bubble
+                           // model), else null: the volume pressure p_volume everywhere
     double *mex;           // [BN] excess mass share of converted cells
     double *rho_if;        // [BN] density after this step, sum_i f*_i as stored, of every
                            // interface cell after the conversions (set by its update,

@@ -260,7 +260,7 @@ __global__ __launch_bounds__(256) void k_curvature(StepArgs a) {
         py_gradient(a.g, c, [&](long long q) { return a.normal[BN + q]; }, t, d1, t);
         py_gradient(a.g, c, [&](long long q) { return a.normal[2 * BN + q]; }, t, t, d2);
         const double km = -0.5 * ((d0 + d1) + d2);
-        a.rhoG[gid] = 3.0 * (a.p_volume + 2.0 * a.sigma * km);
+        a.rhoG[gid] = 3.0 * ((a.pbub ? a.pbub[gid] : a.p_volume) + 2.0 * a.sigma * km);
     }
 }
 
@@ -293,7 +293,7 @@ __device__ __forceinline__ bool interface_part(const StepArgs &a, const long lon
     }
     const double m0 = a.m[gid];
     const double phx = a.phi_cur[gid];
-    const double rg = a.rhoG ? a.rhoG[gid] : 3.0 * a.p_volume;
+    const double rg = a.rhoG ? a.rhoG[gid] : 3.0 * (a.pbub ? a.pbub[gid] : a.p_volume);
     issue_fence();
 #pragma unroll
     for (int i = 1; i < Q; ++i) fn[i] = src[i] >= 0 ? fn[i] : uint8_t(0);

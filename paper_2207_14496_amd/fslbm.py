@@ -22,7 +22,7 @@ SRT, TRT = 0, 1
 REFILL_EQ, REFILL_EQ_NEQ, REFILL_GEQ, REFILL_EXT, REFILL_AVG = 0, 1, 2, 3, 4
 LIQUID, INTERFACE, GAS = 1, 2, 4
 FIELD_FLAGS, FIELD_PDF, FIELD_MASS, FIELD_PHI, FIELD_RHO, FIELD_VEL = (1 << k for k in range(6))
-FIELD_NAMES = ["flags", "pdf", "mass", "phi", "rho", "vel"]
+FIELD_NAMES = ["flags", "pdf", "mass", "phi", "rho", "vel", "bubble_pressure"]
 STORAGE_NAMES = {F64: "f64", F32: "f32", F16: "f16", BF16: "bf16"}
 STORAGE_BYTES = {F64: 8, F32: 4, F16: 2, BF16: 2}
 
@@ -49,7 +49,8 @@ class CParams(ctypes.Structure):
                 ("sigma", ctypes.c_double), ("p_volume", ctypes.c_double),
                 ("eps_phi", ctypes.c_double), ("omega_b", ctypes.POINTER(ctypes.c_double)),
                 ("gravity_b", ctypes.POINTER(ctypes.c_double)), ("stream", ctypes.c_void_p),
-                ("smagorinsky_cs", ctypes.c_double), ("free_slip", ctypes.c_int32)]
+                ("smagorinsky_cs", ctypes.c_double), ("free_slip", ctypes.c_int32),
+                ("bubble_model", ctypes.c_int32)]
 
 
 class CDiag(ctypes.Structure):
@@ -131,6 +132,7 @@ class Params:
     gravity_b: tuple | None = None    # per-domain gravity [B][3]
     smagorinsky_cs: float = 0.0       # Smagorinsky constant (0 = no turbulence model)
     free_slip: int = 0                # walls: 0 no-slip, 1 free-slip (specular)
+    bubble_model: int = 0             # 1: per-bubble volume pressures
 
     @property
     def N(self) -> int:
@@ -147,6 +149,7 @@ class Params:
         p.sigma, p.p_volume, p.eps_phi = float(self.sigma), float(self.p_volume), float(self.eps_phi)
         p.smagorinsky_cs = float(self.smagorinsky_cs)
         p.free_slip = int(self.free_slip)
+        p.bubble_model = int(self.bubble_model)
         keep = []
         if self.omega_b is not None:
             arr = (ctypes.c_double * self.batch)(*[float(v) for v in self.omega_b])
@@ -245,9 +248,10 @@ class Simulation:
         B, N = self.params.batch, self.params.N
         shapes = {"flags": ((B, N), torch.uint8), "pdf": ((B, 19, N), torch.float64),
                   "mass": ((B, N), torch.float64), "phi": ((B, N), torch.float64),
-                  "rho": ((B, N), torch.float64), "vel": ((B, 3, N), torch.float64)}
+                  "rho": ((B, N), torch.float64), "vel": ((B, 3, N), torch.float64),
+                  "bubble_pressure": ((B, N), torch.float64)}
         out, mask = {}, 0
-        ptrs = (ctypes.c_void_p * 6)()
+        ptrs = (ctypes.c_void_p * 7)()
         for name in fields:
             k = FIELD_NAMES.index(name)
             shp, dt = shapes[name]

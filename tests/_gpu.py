@@ -14,7 +14,7 @@ LIQ, IFC, GAS = 1, 2, 4
 def params_from_oracle(p: oracle.Params, storage=fslbm.F64, batch=1, **kw) -> fslbm.Params:
     q = fslbm.Params(p.nx, p.ny, p.nz, batch, tuple(p.periodic), p.collision, storage, p.refill,
                      p.omega, p.trt_lambda, tuple(p.g), p.sigma, p.p_volume, p.eps_phi,
-                     smagorinsky_cs=p.smag_cs, free_slip=p.free_slip)
+                     smagorinsky_cs=p.smag_cs, free_slip=p.free_slip, bubble_model=p.bubble_model)
     for k, v in kw.items():
         setattr(q, k, v)
     return q

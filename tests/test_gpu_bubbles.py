@@ -1,0 +1,77 @@
+"""The bubble model on the GPU against the oracle (Sec. 2.2, volume pressure of
+enclosed gas; reading R31), FP64 storage: flags bit-exact, PDFs, interface
+mass and fill level within 1e-12, bubble pressures within 1e-12 relative (the
+per-bubble sums are atomic on the GPU, in cell order in the oracle)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from _gpu import announce, compare, fields_np, sim_from_states
+from _util import oracle_params, oracle_state
+from paper_2207_14496_amd import setups
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _check(sim, st, what):
+    got = fields_np(sim)
+    compare(got, 0, st, 1e-12, 1e-12, 1e-12, what=what)
+    pb = sim.read(("bubble_pressure",))["bubble_pressure"][0].cpu().numpy()
+    err = np.max(np.abs(pb - st.pbub) / np.maximum(np.abs(st.pbub), 1e-300))
+    assert err <= 1e-12, f"{what}: bubble pressure error {err:.2e}"
+
+
+def test_enclosed_bubble_step_by_step_then_in_calls():
+    s = setups.rising_bubbles()
+    p = oracle_params(s, bubble_model=1)
+    st = oracle_state(s, p)
+    announce("enclosed bubble 24x8x40, bubble model")
+    sim = sim_from_states(p, [st])
+    for k in range(1, 6):
+        sim.step(1)
+        oracle.step(p, st, 1)
+        _check(sim, st, f"bubble step {k}")
+    for k in range(4):
+        sim.step(50)
+        oracle.step(p, st, 50)
+        _check(sim, st, f"bubble step {5 + 50 * (k + 1)}")
+    # compressed: the pressure is above p_V(0)
+    assert st.pbub[st.flags != 1].max() > p.p_volume
+    sim.close()
+
+
+def test_bubbles_that_merge_and_split():
+    s = setups.rising_bubbles(centres=((12.0, 4.0, 9.0), (12.0, 4.0, 18.5)))
+    p = oracle_params(s, bubble_model=1)
+    st = oracle_state(s, p)
+    announce("two stacked bubbles 24x8x40, bubble model, 350 steps")
+    sim = sim_from_states(p, [st])
+    counts = set()
+    for k in range(7):
+        sim.step(50)
+        oracle.step(p, st, 50)
+        _check(sim, st, f"two bubbles step {50 * (k + 1)}")
+        lab = oracle.bubble_labels(p, st.flags)
+        counts.add(len(np.unique(lab[lab >= 0])))
+    assert counts == {1, 2}
+    sim.close()
+
+
+def test_atmosphere_only_dam_break():
+    s = setups.rect_dam_break(40, 6, 24, width=12, height=16, g=2e-4, refill=0)
+    p = oracle_params(s, bubble_model=1)
+    st = oracle_state(s, p)
+    announce("small dam break with the bubble model (atmosphere only)")
+    sim = sim_from_states(p, [st])
+    for k in range(3):
+        sim.step(10)
+        oracle.step(p, st, 10)
+        _check(sim, st, f"atmosphere dam break step {10 * (k + 1)}")
+    sim.close()
