@@ -35,6 +35,9 @@ drop_impact  drop impact 256^3 with surface tension, every storage type, 8000
 adjoint    the reverse mode at full size (64 domains of the 128 x 256 standing
            wave, 4000 steps, sqrt(T) checkpoints): forward and backward wall
            time and cell updates per second.
+bubbles    eight enclosed bubbles rising in a 128 x 64 x 192 box (FP32): step
+           time with and without the bubble model, pressure range, and the
+           total gas amount sum p V over the run.
 """
 from __future__ import annotations
 
@@ -165,6 +168,8 @@ def main():
                     help="only run a 1 GiB elementwise copy kernel 5 times (HBM counter calibration)")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only run the reverse-mode report (64 x 128x256, 4000 steps) and print it")
+    ap.add_argument("--bubbles-only", action="store_true",
+                    help="only run the bubble-model report and print it")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -185,6 +190,10 @@ def main():
     if args.adjoint_only:
         from paper_2207_14496_amd import fslbm, setups
         print(json.dumps({"adjoint": adjoint_report(fslbm, setups, torch)}), flush=True)
+        return
+    if args.bubbles_only:
+        from paper_2207_14496_amd import fslbm, setups
+        print(json.dumps({"bubbles": bubble_report(fslbm, setups, torch)}), flush=True)
         return
     from paper_2207_14496_amd import fslbm, setups
 
@@ -234,6 +243,7 @@ def main():
         result["paper_dam_break"] = paper_dam_break_report(fslbm, setups, torch)
         result["drop_impact"] = drop_impact_report(fslbm, setups, torch, args.drop_steps)
         result["adjoint"] = adjoint_report(fslbm, setups, torch)
+        result["bubbles"] = bubble_report(fslbm, setups, torch)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
         result["cpu_baseline"] = cpu_baseline(setup)
@@ -422,6 +432,52 @@ def adjoint_report(fslbm, setups, torch, T=4000, B=64, x_probe=32):
             "backward_over_forward": round(bwd / fwd, 2),
             "mlups_forward": round(updates / fwd / 1e6, 1), "mlups_backward": round(updates / bwd / 1e6, 1),
             "workspace_gb": round(ws / 1e9, 2), "finite": finite}
+
+
+def bubble_report(fslbm, setups, torch, steps=200, warmup=10):
+    """The bubble model (Sec. 2.2, volume pressure of enclosed gas): eight
+    bubbles of radius 10 rising in a 128 x 64 x 192 liquid box (periodic x, y),
+    FP32 storage.  Step time with the model and without it (the labels, the
+    per-bubble sums and the direct launches are its cost), the bubble pressure
+    range at the end, and the total gas amount sum_k p_k V_k at the start and
+    the end (every bubble is enclosed, so the amount is conserved but for the
+    gas of cells that fill)."""
+    centres = [(32.0 + 64.0 * i, 16.0 + 32.0 * j, 24.0 + 24.0 * k + 6.0 * i)
+               for i in range(2) for j in range(2) for k in range(2)]
+    s = setups.rising_bubbles(nx=128, ny=64, nz=192, centres=centres, radius=10.0, g=2e-5)
+    out = {"workload": "rising-bubbles 128x64x192, 8 bubbles of radius 10, TRT omega=1.7 g=2e-5, "
+                       "f32 shifted PDFs"}
+
+    def amount(sim):
+        f = sim.read(("phi", "bubble_pressure"))
+        gas = torch.clamp(1.0 - f["phi"][0], min=0.0)
+        return float((f["bubble_pressure"][0] * gas).sum()), f
+
+    for bm in (1, 0):
+        sim = fslbm.from_setup(s, storage=fslbm.F32, bubble_model=bm)
+        if bm:
+            a0, _ = amount(sim)
+        sim.step(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        key = "with_model" if bm else "without_model"
+        out[key] = {"ms_per_step": round(dt * 1e3, 4), "mlups_domain": round(s.N / dt / 1e6, 1)}
+        if bm:
+            a1, f = amount(sim)
+            liq = sim.read(("flags",))["flags"][0] == 1
+            pb = f["bubble_pressure"][0][~liq]
+            out["pressure_range"] = [round(float(pb.min()), 6), round(float(pb.max()), 6)]
+            out["amount_start_end"] = [round(a0, 6), round(a1, 6)]
+            out["amount_drift_rel"] = (a1 - a0) / a0
+        sim.close()
+        torch.cuda.empty_cache()
+    log(f"  bubbles: {out['with_model']['ms_per_step']} ms/step with the model, "
+        f"{out['without_model']['ms_per_step']} without; pressures {out['pressure_range']}, "
+        f"amount drift {out['amount_drift_rel']:.2e}")
+    return out
 
 
 def drop_impact_report(fslbm, setups, torch, steps, every=1000):

@@ -17,6 +17,8 @@
 // names) until a pass changes nothing; the host reads the change flag after
 // each pass.  Per-label sums are double atomics.  The model runs with direct
 // launches between the steps (fslbm_step), for the runs with enclosed gas.
+#include <utility>
+
 #include "context.hpp"
 
 namespace fslbm {
@@ -26,6 +28,25 @@ constexpr int BS = 256;
 
 __device__ __forceinline__ bool gas_phase(uint8_t f) { return (f & (F_IF | F_GAS)) != 0; }
 __device__ __forceinline__ double gas_volume(double phi) { return phi < 1.0 ? 1.0 - phi : 0.0; }
+
+// Adds v of every lane whose label l >= 0 into dst[l].  Lanes that share a
+// label (most of a wavefront: its cells are neighbours) are summed in
+// registers first, so there is one atomic per label and wavefront: atomics on
+// one address serialise, and a bubble's cells all add to one.  Every lane of
+// the wavefront calls it.
+__device__ __forceinline__ void wave_add_by_label(int32_t l, double v, double *dst) {
+    unsigned long long todo = __ballot(l >= 0);
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int32_t lk = __shfl(l, leader);
+        const bool mine = l == lk;
+        double sum = mine ? v : 0.0;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+        if (__lane_id() == leader) atomicAdd(dst + lk, sum);
+        todo &= ~__ballot(mine);
+    }
+}
 
 // Every gas and interface cell labelled with its own index, liquid -1.
 __global__ __launch_bounds__(BS) void k_bub_seed(StepArgs a, int32_t *lab) {
@@ -62,21 +83,18 @@ __global__ __launch_bounds__(BS) void k_bub_pass(StepArgs a, int32_t *lab, int32
 __global__ __launch_bounds__(BS) void k_bub_volume(StepArgs a, const int32_t *lab, const double *phi,
                                                    double *V, int32_t *atm) {
     const long long gid = (long long)blockIdx.x * BS + threadIdx.x;
-    if (gid >= a.g.BN) return;
-    const int32_t l = lab[gid];
-    if (l < 0) return;
-    atomicAdd(V + l, gas_volume(phi[gid]));
-    if (atm && decode(a.g, gid).z == a.g.nz - 1) atm[l] = 1;
+    const int32_t l = gid < a.g.BN ? lab[gid] : -1;
+    wave_add_by_label(l, l >= 0 ? gas_volume(phi[gid]) : 0.0, V);
+    if (l >= 0 && atm && decode(a.g, gid).z == a.g.nz - 1) atm[l] = 1;
 }
 
 // Gas volume of every start bubble's cells that are still gas or interface.
 __global__ __launch_bounds__(BS) void k_bub_kept(StepArgs a, const int32_t *lab0, const int32_t *lab1,
                                                  const double *phi, double *kept) {
     const long long gid = (long long)blockIdx.x * BS + threadIdx.x;
-    if (gid >= a.g.BN) return;
-    const int32_t b = lab0[gid];
-    if (b < 0 || lab1[gid] < 0) return;
-    atomicAdd(kept + b, gas_volume(phi[gid]));
+    int32_t b = gid < a.g.BN ? lab0[gid] : -1;
+    if (b >= 0 && lab1[gid] < 0) b = -1;
+    wave_add_by_label(b, b >= 0 ? gas_volume(phi[gid]) : 0.0, kept);
 }
 
 // Each start bubble's amount p V, handed to the end bubbles by gas volume.
@@ -84,10 +102,12 @@ __global__ __launch_bounds__(BS) void k_bub_amount(StepArgs a, const int32_t *la
                                                    const double *phi, const double *pbub, const double *V0,
                                                    const double *kept, double *amount) {
     const long long gid = (long long)blockIdx.x * BS + threadIdx.x;
-    if (gid >= a.g.BN) return;
-    const int32_t b = lab0[gid], k = lab1[gid];
-    if (b < 0 || k < 0 || !(kept[b] > 0.0)) return;
-    atomicAdd(amount + k, pbub[b] * V0[b] * gas_volume(phi[gid]) / kept[b]);
+    const int32_t b = gid < a.g.BN ? lab0[gid] : -1;
+    int32_t k = gid < a.g.BN ? lab1[gid] : -1;
+    double v = 0.0;
+    if (b < 0 || k < 0 || !(kept[b >= 0 ? b : 0] > 0.0)) k = -1;
+    else v = pbub[b] * V0[b] * gas_volume(phi[gid]) / kept[b];
+    wave_add_by_label(k, v, amount);
 }
 
 // The pressures of the end bubbles (0 on liquid cells).
@@ -133,6 +153,13 @@ bool label(fslbm_ctx *c, const StepArgs &a, int32_t *lab) {
 }  // namespace
 
 bool bubble_begin(fslbm_ctx *c) {
+    if (c->bub_ready) {
+        // the step's start is the last step's end: its labels and volumes
+        std::swap(c->L.blab0, c->L.blab1);
+        std::swap(c->L.bV0, c->L.bV1);
+        c->bub_ready = false;
+        return true;
+    }
     const StepArgs a = make_args(c, int(c->t & 1));
     const size_t BN = size_t(a.g.BN);
     int32_t *lab0 = at<int32_t>(c, c->L.blab0);
@@ -168,11 +195,13 @@ bool bubble_end(fslbm_ctx *c) {
     hipLaunchKernelGGL(k_bub_assign, dim3(nb), dim3(BS), 0, c->stream, a, lab1, static_cast<const double *>(V1),
                        static_cast<const double *>(amount), static_cast<const int32_t *>(atm), pbub);
     if (!hip_ok(c, hipGetLastError(), "bubble kernels")) return false;
+    c->bub_ready = true;
     // the refills may have opened tiles: keep the bulk grid large enough
     return refresh_bulk_grid(c);
 }
 
 bool bubble_reset(fslbm_ctx *c) {
+    c->bub_ready = false;
     const StepArgs a = make_args(c, int(c->t & 1));
     hipLaunchKernelGGL(k_bub_reset, dim3(blocks(a)), dim3(BS), 0, c->stream, a, at<double>(c, c->L.pbub));
     return hip_ok(c, hipGetLastError(), "k_bub_reset");

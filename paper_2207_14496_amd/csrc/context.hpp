@@ -51,6 +51,8 @@ struct fslbm_ctx {
     hipGraphExec_t exec[4] = {nullptr, nullptr, nullptr, nullptr};   // [parity + 2 * pending]
     bool pending = false;            // the last step's excess-mass redistribution has not run yet
     int bulk_grid = 1024;            // workgroups of the bulk kernel (tile-list stride)
+    bool bub_ready = false;          // the bubble labels and volumes of the last step's end
+                                     // are those of the next step's start
     fslbm::AdjointRun adj;
     fslbm_status status = FSLBM_OK;
     std::string err = "no error";
