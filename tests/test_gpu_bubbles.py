@@ -75,3 +75,43 @@ def test_atmosphere_only_dam_break():
         oracle.step(p, st, 10)
         _check(sim, st, f"atmosphere dam break step {10 * (k + 1)}")
     sim.close()
+
+
+def test_enclosed_bubble_with_surface_tension():
+    """sigma != 0: the curvature kernel adds the Laplace term to the cell's
+    bubble pressure (rho_G = 3 (p_bubble + 2 sigma kappa))."""
+    s = setups.rising_bubbles()
+    p = oracle_params(s, bubble_model=1, sigma=2e-3)
+    st = oracle_state(s, p)
+    announce("enclosed bubble with surface tension, bubble model")
+    sim = sim_from_states(p, [st])
+    for k in range(1, 4):
+        sim.step(1)
+        oracle.step(p, st, 1)
+        _check(sim, st, f"bubble with sigma step {k}")
+    sim.step(40)
+    oracle.step(p, st, 40)
+    _check(sim, st, "bubble with sigma step 43")
+    sim.close()
+
+
+def test_batch_of_two_domains_with_bubbles():
+    """Labels are global cell indices and never cross domains: two different
+    bubble states in one launch, each against its own oracle run."""
+    s1 = setups.rising_bubbles()
+    s2 = setups.rising_bubbles(centres=((12.0, 4.0, 9.0), (12.0, 4.0, 18.5)))
+    p = oracle_params(s1, bubble_model=1)
+    st1, st2 = oracle_state(s1, p), oracle_state(s2, p)
+    announce("two domains with bubbles in one launch")
+    sim = sim_from_states(p, [st1, st2])
+    for k in range(3):
+        sim.step(50)
+        oracle.step(p, st1, 50)
+        oracle.step(p, st2, 50)
+        got = fields_np(sim)
+        pb = sim.read(("bubble_pressure",))["bubble_pressure"].cpu().numpy()
+        for b, st in enumerate((st1, st2)):
+            compare(got, b, st, 1e-12, 1e-12, 1e-12, what=f"domain {b} step {50 * (k + 1)}")
+            err = np.max(np.abs(pb[b] - st.pbub) / np.maximum(np.abs(st.pbub), 1e-300))
+            assert err <= 1e-12, f"domain {b}: bubble pressure error {err:.2e}"
+    sim.close()
