@@ -70,7 +70,7 @@ bool make_layout(const fslbm_params &p, Layout &L) {
     L.bkept = bub ? take(size_t(BN) * 8) : 0;
     L.bamount = bub ? take(size_t(BN) * 8) : 0;
     L.batm = bub ? take(size_t(BN) * 4) : 0;
-    L.bflag = bub ? take(256) : 0;
+    L.bflag = bub ? take(size_t(bubble_pass_cap(p)) * 4) : 0;
     L.total = off;
     return true;
 }
@@ -540,6 +540,10 @@ bool refresh_bulk_grid(fslbm_ctx *c) {
     if (!hip_ok(c, hipMemcpy(&n, at<int32_t>(c, c->L.cnt) + C_TILES, 4, hipMemcpyDeviceToHost),
                 "hipMemcpy(tile count)"))
         return false;
+    return resize_bulk_grid(c, n);
+}
+
+bool resize_bulk_grid(fslbm_ctx *c, int32_t n) {
     // one wavefront per tile, four per workgroup, room for the list to double
     const long long total = tile_count((long long)c->p.nx * c->p.ny * c->p.nz * c->p.batch);
     const long long waves = std::min<long long>(total, std::max<long long>(4096, 2LL * n));

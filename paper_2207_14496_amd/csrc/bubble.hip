@@ -14,10 +14,14 @@
 // Labels are global cell indices: every set ends up labelled with its
 // smallest cell index.  They come from passes of label propagation (each cell
 // takes the smallest label around it, then the label of the cell its label
-// names) until a pass changes nothing; the host reads the change flag after
-// each pass.  Per-label sums are double atomics.  The model runs with direct
-// launches between the steps (fslbm_step), for the runs with enclosed gas.
+// names) until a pass changes nothing.  Every pass has its own change flag and
+// returns at once when the pass before it changed nothing, so the host
+// launches a batch of passes (as many as the last labelling took) and reads
+// the flags once.  Per-label sums are double atomics.  The model runs with
+// direct launches between the steps (fslbm_step), for the runs with enclosed gas.
+#include <algorithm>
 #include <utility>
+#include <vector>
 
 #include "context.hpp"
 
@@ -48,18 +52,26 @@ __device__ __forceinline__ void wave_add_by_label(int32_t l, double v, double *d
     }
 }
 
-// Every gas and interface cell labelled with its own index, liquid -1.
-__global__ __launch_bounds__(BS) void k_bub_seed(StepArgs a, int32_t *lab) {
+// Every gas and interface cell labelled with its own index, liquid -1; the
+// passes' change flags and the per-label sums of this labelling cleared.
+__global__ __launch_bounds__(BS) void k_bub_seed(StepArgs a, int32_t *lab, int32_t *flags, int nflags,
+                                                 double *z0, double *z1, double *z2, int32_t *z3) {
     const long long gid = (long long)blockIdx.x * BS + threadIdx.x;
+    for (long long i = gid; i < nflags; i += (long long)gridDim.x * BS) flags[i] = 0;
     if (gid >= a.g.BN) return;
     lab[gid] = gas_phase(a.flags[gid]) ? int32_t(gid) : -1;
+    if (z0) z0[gid] = 0.0;
+    if (z1) z1[gid] = 0.0;
+    if (z2) z2[gid] = 0.0;
+    if (z3) z3[gid] = 0;
 }
 
-// One propagation pass.  Labels only ever name gas or interface cells of the
+// Propagation pass k.  Labels only ever name gas or interface cells of the
 // same set and only fall, so the fixed point is each set's smallest index.
-__global__ __launch_bounds__(BS) void k_bub_pass(StepArgs a, int32_t *lab, int32_t *changed) {
+// A pass after one that changed nothing has nothing to do.
+__global__ __launch_bounds__(BS) void k_bub_pass(StepArgs a, int32_t *lab, int32_t *flags, int k) {
     const long long gid = (long long)blockIdx.x * BS + threadIdx.x;
-    if (gid >= a.g.BN) return;
+    if (gid >= a.g.BN || (k > 0 && flags[k - 1] == 0)) return;
     const int32_t l0 = lab[gid];
     if (l0 < 0) return;
     const Cell c = decode(a.g, gid);
@@ -75,26 +87,25 @@ __global__ __launch_bounds__(BS) void k_bub_pass(StepArgs a, int32_t *lab, int32
     m = (mm >= 0 && mm < m) ? mm : m;
     if (m < l0) {
         lab[gid] = m;
-        *changed = 1;
+        flags[k] = 1;
     }
 }
 
-// Gas volume per label; with top, the labels that reach the top layer.
-__global__ __launch_bounds__(BS) void k_bub_volume(StepArgs a, const int32_t *lab, const double *phi,
-                                                   double *V, int32_t *atm) {
+// Gas volume per label of lab1; with atm, the labels that reach the top layer;
+// with lab0, the gas volume of every start bubble's cells that are still gas
+// or interface.
+__global__ __launch_bounds__(BS) void k_bub_volume(StepArgs a, const int32_t *lab1, const double *phi,
+                                                   double *V, int32_t *atm, const int32_t *lab0,
+                                                   double *kept) {
     const long long gid = (long long)blockIdx.x * BS + threadIdx.x;
-    const int32_t l = gid < a.g.BN ? lab[gid] : -1;
-    wave_add_by_label(l, l >= 0 ? gas_volume(phi[gid]) : 0.0, V);
+    const int32_t l = gid < a.g.BN ? lab1[gid] : -1;
+    const double gv = l >= 0 ? gas_volume(phi[gid]) : 0.0;
+    wave_add_by_label(l, gv, V);
     if (l >= 0 && atm && decode(a.g, gid).z == a.g.nz - 1) atm[l] = 1;
-}
-
-// Gas volume of every start bubble's cells that are still gas or interface.
-__global__ __launch_bounds__(BS) void k_bub_kept(StepArgs a, const int32_t *lab0, const int32_t *lab1,
-                                                 const double *phi, double *kept) {
-    const long long gid = (long long)blockIdx.x * BS + threadIdx.x;
-    int32_t b = gid < a.g.BN ? lab0[gid] : -1;
-    if (b >= 0 && lab1[gid] < 0) b = -1;
-    wave_add_by_label(b, b >= 0 ? gas_volume(phi[gid]) : 0.0, kept);
+    if (lab0) {
+        const int32_t b = l >= 0 ? lab0[gid] : -1;
+        wave_add_by_label(b, gv, kept);
+    }
 }
 
 // Each start bubble's amount p V, handed to the end bubbles by gas volume.
@@ -129,22 +140,36 @@ __global__ __launch_bounds__(BS) void k_bub_reset(StepArgs a, double *pbub) {
 
 unsigned blocks(const StepArgs &a) { return unsigned((a.g.BN + BS - 1) / BS); }
 
-// Label the gas and interface sets of the current flags into lab.
-bool label(fslbm_ctx *c, const StepArgs &a, int32_t *lab) {
-    int32_t *flag = at<int32_t>(c, c->L.bflag);
-    hipLaunchKernelGGL(k_bub_seed, dim3(blocks(a)), dim3(BS), 0, c->stream, a, lab);
+// Label the gas and interface sets of the current flags into lab and clear
+// the sums z0..z3 (each BN entries, or null).  With tiles, also read back the
+// fluid-tile count in the same synchronisation and resize the bulk grid.
+bool label(fslbm_ctx *c, const StepArgs &a, int32_t *lab, double *z0, double *z1, double *z2, int32_t *z3,
+           bool tiles) {
+    int32_t *flags = at<int32_t>(c, c->L.bflag);
+    const int cap = int(bubble_pass_cap(c->p));
+    hipLaunchKernelGGL(k_bub_seed, dim3(blocks(a)), dim3(BS), 0, c->stream, a, lab, flags, cap, z0, z1, z2, z3);
     if (!hip_ok(c, hipGetLastError(), "k_bub_seed")) return false;
-    // each pass lowers at least one label while any is not final
-    const long long cap = 8LL * (c->p.nx + c->p.ny + c->p.nz) + 1024;
-    for (long long it = 0; it < cap; ++it) {
-        int32_t h = 0;
-        if (!hip_ok(c, hipMemsetAsync(flag, 0, 4, c->stream), "hipMemset(bubble flag)")) return false;
-        hipLaunchKernelGGL(k_bub_pass, dim3(blocks(a)), dim3(BS), 0, c->stream, a, lab, flag);
+    std::vector<int32_t> h;
+    int done = 0, batch = std::max(2, c->bub_passes);
+    while (done < cap) {
+        const int n = std::min(batch, cap - done);
+        for (int j = 0; j < n; ++j)
+            hipLaunchKernelGGL(k_bub_pass, dim3(blocks(a)), dim3(BS), 0, c->stream, a, lab, flags, done + j);
+        h.assign(size_t(n) + 1, 0);
         if (!hip_ok(c, hipGetLastError(), "k_bub_pass") ||
-            !hip_ok(c, hipMemcpyAsync(&h, flag, 4, hipMemcpyDeviceToHost, c->stream), "hipMemcpy(bubble flag)") ||
+            !hip_ok(c, hipMemcpyAsync(h.data(), flags + done, size_t(n) * 4, hipMemcpyDeviceToHost, c->stream),
+                    "hipMemcpy(bubble flags)") ||
+            (tiles && !hip_ok(c, hipMemcpyAsync(&h[n], at<int32_t>(c, c->L.cnt) + C_TILES, 4,
+                                                hipMemcpyDeviceToHost, c->stream), "hipMemcpy(tile count)")) ||
             !hip_ok(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize"))
             return false;
-        if (!h) return true;
+        const int first_zero = int(std::find(h.begin(), h.begin() + n, 0) - h.begin());
+        if (first_zero < n) {
+            c->bub_passes = done + first_zero + 1;
+            return !tiles || resize_bulk_grid(c, h[n]);
+        }
+        done += n;
+        batch *= 2;
     }
     fail(c, FSLBM_EDEVICE, "bubble labels did not settle");
     return false;
@@ -161,34 +186,29 @@ bool bubble_begin(fslbm_ctx *c) {
         return true;
     }
     const StepArgs a = make_args(c, int(c->t & 1));
-    const size_t BN = size_t(a.g.BN);
     int32_t *lab0 = at<int32_t>(c, c->L.blab0);
     double *V0 = at<double>(c, c->L.bV0);
-    if (!label(c, a, lab0)) return false;
-    if (!hip_ok(c, hipMemsetAsync(V0, 0, BN * 8, c->stream), "hipMemset(bubble volumes)")) return false;
+    if (!label(c, a, lab0, V0, nullptr, nullptr, nullptr, false)) return false;
     hipLaunchKernelGGL(k_bub_volume, dim3(blocks(a)), dim3(BS), 0, c->stream, a, lab0, a.phi_cur, V0,
-                       static_cast<int32_t *>(nullptr));
+                       static_cast<int32_t *>(nullptr), static_cast<const int32_t *>(nullptr),
+                       static_cast<double *>(nullptr));
     return hip_ok(c, hipGetLastError(), "k_bub_volume");
 }
 
 bool bubble_end(fslbm_ctx *c) {
     // after the step: phi_cur of the next step's arguments is the step's result
     const StepArgs a = make_args(c, int(c->t & 1));
-    const size_t BN = size_t(a.g.BN);
     int32_t *lab0 = at<int32_t>(c, c->L.blab0), *lab1 = at<int32_t>(c, c->L.blab1);
     int32_t *atm = at<int32_t>(c, c->L.batm);
     double *V0 = at<double>(c, c->L.bV0), *V1 = at<double>(c, c->L.bV1);
     double *kept = at<double>(c, c->L.bkept), *amount = at<double>(c, c->L.bamount);
     double *pbub = at<double>(c, c->L.pbub);
-    if (!label(c, a, lab1)) return false;
-    bool ok = hip_ok(c, hipMemsetAsync(V1, 0, BN * 8, c->stream), "hipMemset") &&
-              hip_ok(c, hipMemsetAsync(kept, 0, BN * 8, c->stream), "hipMemset") &&
-              hip_ok(c, hipMemsetAsync(amount, 0, BN * 8, c->stream), "hipMemset") &&
-              hip_ok(c, hipMemsetAsync(atm, 0, BN * 4, c->stream), "hipMemset");
-    if (!ok) return false;
+    // the refills may have opened tiles: the bulk grid is resized from the
+    // tile count read with the labels
+    if (!label(c, a, lab1, V1, kept, amount, atm, true)) return false;
     const unsigned nb = blocks(a);
-    hipLaunchKernelGGL(k_bub_volume, dim3(nb), dim3(BS), 0, c->stream, a, lab1, a.phi_cur, V1, atm);
-    hipLaunchKernelGGL(k_bub_kept, dim3(nb), dim3(BS), 0, c->stream, a, lab0, lab1, a.phi_cur, kept);
+    hipLaunchKernelGGL(k_bub_volume, dim3(nb), dim3(BS), 0, c->stream, a, lab1, a.phi_cur, V1, atm,
+                       static_cast<const int32_t *>(lab0), kept);
     hipLaunchKernelGGL(k_bub_amount, dim3(nb), dim3(BS), 0, c->stream, a, lab0, lab1, a.phi_cur,
                        static_cast<const double *>(pbub), static_cast<const double *>(V0),
                        static_cast<const double *>(kept), amount);
@@ -196,8 +216,13 @@ bool bubble_end(fslbm_ctx *c) {
                        static_cast<const double *>(amount), static_cast<const int32_t *>(atm), pbub);
     if (!hip_ok(c, hipGetLastError(), "bubble kernels")) return false;
     c->bub_ready = true;
-    // the refills may have opened tiles: keep the bulk grid large enough
-    return refresh_bulk_grid(c);
+    return true;
+}
+
+long long bubble_pass_cap(const fslbm_params &p) {
+    // each pass lowers at least one label while any is not final; pointer
+    // jumping makes the passes far fewer than a set's diameter
+    return 8LL * (p.nx + p.ny + p.nz) + 1024;
 }
 
 bool bubble_reset(fslbm_ctx *c) {

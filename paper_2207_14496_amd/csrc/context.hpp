@@ -53,6 +53,7 @@ struct fslbm_ctx {
     int bulk_grid = 1024;            // workgroups of the bulk kernel (tile-list stride)
     bool bub_ready = false;          // the bubble labels and volumes of the last step's end
                                      // are those of the next step's start
+    int bub_passes = 0;              // label passes of the last labelling, the unchanged one included
     fslbm::AdjointRun adj;
     fslbm_status status = FSLBM_OK;
     std::string err = "no error";
@@ -89,12 +90,16 @@ bool load_state(fslbm_ctx *c, const uint8_t *flags, const double *phi, const dou
 // tile total) if the list has outgrown it.  Needs a synchronised stream; drops
 // the captured graphs when the grid changes.
 bool refresh_bulk_grid(fslbm_ctx *c);
+// The same from a fluid-tile count the caller has read back.
+bool resize_bulk_grid(fslbm_ctx *c, int32_t fluid_tiles);
 
 // Enqueue the canonical read-back of the fields in `mask` (no synchronisation).
 bool enqueue_read(fslbm_ctx *c, uint32_t mask, void *const *dst);
 
 // Bubble model (bubble_model = 1): the bubbles and their volumes at the start
 // of a step, and their pressures at its end.  Both synchronise the stream.
+// The label passes' change flags take bubble_pass_cap(p) int32 entries.
+long long bubble_pass_cap(const fslbm_params &p);
 bool bubble_begin(fslbm_ctx *c);
 bool bubble_end(fslbm_ctx *c);
 // Every gas and interface cell at p_volume (after a state is loaded).
