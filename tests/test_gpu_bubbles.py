@@ -115,3 +115,30 @@ def test_batch_of_two_domains_with_bubbles():
             err = np.max(np.abs(pb[b] - st.pbub) / np.maximum(np.abs(st.pbub), 1e-300))
             assert err <= 1e-12, f"domain {b}: bubble pressure error {err:.2e}"
     sim.close()
+
+
+def test_fp32_storage_keeps_boyle_law():
+    """FP32 shifted populations (m, phi and the bubble sums stay FP64): the
+    bubble keeps p V = p_V(0) V(0) to rounding, and its pressure stays within
+    1e-5 of the FP64 oracle's after 200 steps."""
+    from paper_2207_14496_amd import fslbm
+    s = setups.rising_bubbles()
+    p = oracle_params(s, bubble_model=1)
+    st = oracle_state(s, p)
+    gas = st.flags != 1
+    pv0 = p.p_volume * float(np.sum(np.maximum(0.0, 1.0 - st.phi[gas])))
+    announce("enclosed bubble 24x8x40, bubble model, f32 storage, 200 steps")
+    sim = sim_from_states(p, [st], storage=fslbm.F32)
+    sim.step(200)
+    oracle.step(p, st, 200)
+    got = fields_np(sim)
+    pb = sim.read(("bubble_pressure",))["bubble_pressure"][0].cpu().numpy()
+    sim.close()
+    g = got["flags"][0] != 1
+    pr = np.unique(pb[g])
+    assert len(pr) == 1, "one enclosed bubble, one pressure"
+    v = float(np.sum(np.maximum(0.0, 1.0 - got["phi"][0][g])))
+    assert abs(pr[0] * v - pv0) <= 1e-11 * pv0
+    po = np.unique(st.pbub[st.flags != 1])
+    assert len(po) == 1 and abs(pr[0] - po[0]) <= 1e-5 * po[0]
+    assert pr[0] > p.p_volume
