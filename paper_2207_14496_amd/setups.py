@@ -373,6 +373,82 @@ def random_interface_state(nx, ny, nz, seed, periodic=(1, 1, 1), fill=0.5, omega
     return s
 
 
+def _far_from_other_types(flags3, kind, periodic, reach=2):
+    """Cells of type ``kind`` whose whole (2 reach + 1)^3 neighbourhood inside
+    the box is of that type (periodic axes wrap, walls cut the box)."""
+    ok = flags3 == kind
+    nz, ny, nx = flags3.shape
+    for dz, dy, dx in np.ndindex(2 * reach + 1, 2 * reach + 1, 2 * reach + 1):
+        sh = flags3 == kind
+        for axis, d, per, n in ((0, dz - reach, periodic[2], nz), (1, dy - reach, periodic[1], ny),
+                                (2, dx - reach, periodic[0], nx)):
+            if d == 0:
+                continue
+            sh = np.roll(sh, -d, axis=axis)
+            if not per:
+                cut = [slice(None)] * 3
+                cut[axis] = slice(n - d, n) if d > 0 else slice(0, -d)
+                sh[tuple(cut)] = True        # cells beyond a wall do not count
+        ok &= sh
+    return ok
+
+
+def planted_state(nx, ny, nz, seed, drops=3, bubbles=3, depth=0.45, omega=1.7,
+                  g=(0.0, 0.0, -1e-4), collision=0, refill=0, periodic=(1, 1, 0),
+                  base=None) -> Setup:
+    """A seeded pool with isolated interface cells planted where no interface
+    cell can reach them within a step: ``drops`` single cells in the gas (fill
+    level -0.05 .. -0.02, so they empty at once) and ``bubbles`` single cells
+    in the liquid (fill level 1.05 .. 1.10, so they fill at once), each at
+    least three cells from any cell of another type and from each other.
+    ``base`` = "liquid" or "gas" replaces the pool by a box of that type,
+    which only gets the planted cells of its own type.
+    The pool's own surface is noisy, with fill levels straddling both
+    thresholds and small random velocities, as in random_interface_state."""
+    rng = np.random.default_rng(seed)
+    s = Setup("planted", nx, ny, nz, periodic, collision, omega, g, refill=refill)
+    zc = np.arange(nz, dtype=np.float64)[:, None, None]
+    if base is None:
+        bump = rng.uniform(-0.08 * nz, 0.08 * nz, size=(ny, nx))
+        phi3 = np.clip(depth * nz + bump[None] - zc, 0.0, 1.0)
+    else:
+        phi3 = np.full((nz, ny, nx), 1.0 if base == "liquid" else 0.0)
+        drops, bubbles = (0, bubbles) if base == "liquid" else (drops, 0)
+    s.u = None
+    s = _finish(s, phi3, np.ones((nz, ny, nx)))
+    itf = s.flags == INTERFACE
+    s.phi[itf] = rng.uniform(-0.05, 1.05, size=int(itf.sum()))
+    s.rho = np.where(s.flags == GAS, 1.0, 1.0 + rng.uniform(-0.01, 0.01, s.N))
+    s.u = np.where((s.flags == GAS)[None], 0.0, rng.uniform(-0.02, 0.02, (3, s.N)))
+    f3 = s.flags.reshape(nz, ny, nx)
+    taken = np.zeros((nz, ny, nx), bool)
+    planted = []
+    for kind, count, lo, hi in ((GAS, drops, -0.05, -0.02), (LIQUID, bubbles, 1.05, 1.10)):
+        cand = np.argwhere(_far_from_other_types(f3, kind, periodic, reach=3))
+        rng.shuffle(cand)
+        placed = 0
+        for z, y, x in cand:
+            if placed == count:
+                break
+            near = taken[max(z - 3, 0):z + 4, :, :]
+            dy = np.minimum(np.abs(np.arange(ny) - y), ny - np.abs(np.arange(ny) - y))
+            dx = np.minimum(np.abs(np.arange(nx) - x), nx - np.abs(np.arange(nx) - x))
+            if np.any(near[:, (dy <= 3)][:, :, dx <= 3]):
+                continue
+            n = (z * ny + y) * nx + x
+            taken[z, y, x] = True
+            s.flags[n] = INTERFACE
+            s.phi[n] = rng.uniform(lo, hi)
+            s.rho[n] = 1.0 + (0.0 if kind == GAS else rng.uniform(-0.01, 0.01))
+            s.u[:, n] = rng.uniform(-0.02, 0.02, 3)
+            planted.append(int(n))
+            placed += 1
+        if placed < count:
+            raise ValueError(f"room for only {placed} of {count} planted cells")
+    s.meta = dict(planted=planted)
+    return s
+
+
 def config(name: str, refill: int = 0) -> Setup:
     """The named synthetic workloads (sizes as stated in their docstrings)."""
     if name == "standing-wave-64":
