@@ -35,7 +35,8 @@
  *   (0,1,-1) (0,-1,1); the opposite of i >= 1 is i+1 (odd i) or i-1 (even i).
  * - Memory: the caller owns every byte.  The library never allocates device
  *   memory; it carves the caller's workspace (fslbm_workspace_bytes) and keeps
- *   only a small host-side context.  Inputs are read, never retained (the
+ *   only a small host-side context.  (fslbm_init_static instead takes a static
+ *   array that the library's code object holds on each device.)  Inputs are read, never retained (the
  *   adjoint target pointer is the one exception, see fslbm_adjoint_spec).
  * - Streams: all device work is enqueued on params.stream (a hipStream_t;
  *   NULL = the null stream).  fslbm_init, fslbm_read_fields and
@@ -183,6 +184,30 @@ fslbm_status fslbm_init(const fslbm_params *params, void *workspace, size_t byte
                         const uint8_t *flags, const double *phi, const double *rho,
                         const double *u, const double *pdf, const double *mass,
                         fslbm_ctx **out);
+
+/*
+ * Allocation-free variant of fslbm_init, for callers that cannot allocate
+ * device memory (code running under stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The context's workspace is the library's
+ * own static device array of FSLBM_STATIC_WORKSPACE_BYTES (64 MiB), one per
+ * device, held from the first use on a device until the process ends; the
+ * call uses the array of the current device (params->stream must belong to
+ * it).  Arguments and validation as fslbm_init, without workspace and bytes;
+ * the call calls no hipMalloc or hipFree and allocates no device memory
+ * (only the small host-side context).
+ * Errors: FSLBM_ENOMEM (with the needed size in fslbm_last_error(NULL)) when
+ * fslbm_workspace_bytes exceeds the array; FSLBM_ESTATE while another context
+ * made by this call is alive on the device (one at a time: they would share
+ * the array); FSLBM_EDEVICE without a current device.  The array keeps what
+ * the last context left; the call clears whatever must start at zero.
+ * fslbm_destroy of such a context waits for its stream, then frees the array
+ * for the next call.  Calls on the context from several host threads at once
+ * race, as on any context.
+ */
+#define FSLBM_STATIC_WORKSPACE_BYTES 67108864u
+fslbm_status fslbm_init_static(const fslbm_params *params, const uint8_t *flags, const double *phi,
+                               const double *rho, const double *u, const double *pdf,
+                               const double *mass, fslbm_ctx **out);
 
 /* Enqueue nsteps >= 0 FSLBM time steps (a)-(e) on the context's stream.
  * Asynchronous: device-side failures surface at the next synchronising call.

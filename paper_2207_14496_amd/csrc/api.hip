@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -99,6 +100,20 @@ const char *validate(const fslbm_params *p) {
 }
 
 std::string g_init_error = "no error";
+
+// The workspace of fslbm_init_static: one array per device, held until the
+// process ends.  In host code the array's name is only a host-side stand-in;
+// every host use goes through the device address that hipGetSymbolAddress
+// returns for the current device, kept per device in g_static.
+constexpr size_t STATIC_WS_BYTES = size_t(FSLBM_STATIC_WORKSPACE_BYTES);
+static __device__ __align__(256) unsigned char scratch[STATIC_WS_BYTES];
+constexpr int STATIC_MAX_DEVICES = 64;
+struct StaticSlot {
+    void *ptr = nullptr;          // device address of `scratch` on this device
+    fslbm_ctx *owner = nullptr;   // the live context that uses it, if any
+};
+std::mutex g_static_mu;
+StaticSlot g_static[STATIC_MAX_DEVICES];
 
 // ------------------------------------------------------------------ init kernels
 
@@ -641,6 +656,54 @@ fslbm_status fslbm_init(const fslbm_params *params, void *workspace, size_t byte
     return FSLBM_OK;
 }
 
+fslbm_status fslbm_init_static(const fslbm_params *params, const uint8_t *flags, const double *phi,
+                               const double *rho, const double *u, const double *pdf,
+                               const double *mass, fslbm_ctx **out) {
+    if (out) *out = nullptr;
+    const char *why = validate(params);
+    if (!why && !out) why = "out is NULL";
+    if (why) { g_init_error = why; return FSLBM_EINVAL; }
+    Layout L;
+    make_layout(*params, L);
+    if (L.total > STATIC_WS_BYTES) {
+        g_init_error = "fslbm_init_static: these parameters need " + std::to_string(L.total) +
+                       " bytes of workspace, more than the static workspace's " +
+                       std::to_string(STATIC_WS_BYTES);
+        return FSLBM_ENOMEM;
+    }
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= STATIC_MAX_DEVICES) {
+        g_init_error = "fslbm_init_static: no current device (or a device index above 63)";
+        return FSLBM_EDEVICE;
+    }
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    StaticSlot &slot = g_static[dev];
+    if (!slot.ptr) {
+        // once per device, with that device current
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            g_init_error = std::string("fslbm_init_static: hipGetSymbolAddress: ") + hipGetErrorString(e);
+            return FSLBM_EDEVICE;
+        }
+        slot.ptr = ptr;
+    }
+    if (slot.owner) {
+        g_init_error = "fslbm_init_static: another live context uses this device's static workspace "
+                       "(fslbm_destroy it first)";
+        return FSLBM_ESTATE;
+    }
+    // fslbm_init clears every part of the workspace that must start at zero,
+    // so what the last context left in the array does not matter
+    fslbm_ctx *c = nullptr;
+    const fslbm_status st = fslbm_init(params, slot.ptr, STATIC_WS_BYTES, flags, phi, rho, u, pdf, mass, &c);
+    if (st != FSLBM_OK) return st;
+    c->static_dev = dev;
+    slot.owner = c;
+    *out = c;
+    return FSLBM_OK;
+}
+
 fslbm_status fslbm_step(fslbm_ctx *c, int32_t nsteps) {
     if (!c) return FSLBM_EINVAL;
     if (c->status != FSLBM_OK) return c->status;
@@ -839,6 +902,12 @@ void fslbm_destroy(fslbm_ctx *c) {
     if (!c) return;
     drop_graphs(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->static_dev >= 0) {
+        // the next static context may use another stream: let this one's work end first
+        (void)hipStreamSynchronize(c->stream);
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        if (g_static[c->static_dev].owner == c) g_static[c->static_dev].owner = nullptr;
+    }
     delete c;
 }
 

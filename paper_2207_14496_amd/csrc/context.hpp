@@ -55,6 +55,8 @@ struct fslbm_ctx {
                                      // are those of the next step's start
     int bub_passes = 0;              // label passes of the last labelling, the unchanged one included
     fslbm::AdjointRun adj;
+    int static_dev = -1;             // device whose static workspace backs this context
+                                     // (fslbm_init_static), else -1
     fslbm_status status = FSLBM_OK;
     std::string err = "no error";
 };

@@ -25,9 +25,11 @@ FIELD_FLAGS, FIELD_PDF, FIELD_MASS, FIELD_PHI, FIELD_RHO, FIELD_VEL = (1 << k fo
 FIELD_NAMES = ["flags", "pdf", "mass", "phi", "rho", "vel", "bubble_pressure"]
 STORAGE_NAMES = {F64: "f64", F32: "f32", F16: "f16", BF16: "bf16"}
 STORAGE_BYTES = {F64: 8, F32: 4, F16: 2, BF16: 2}
+STATIC_WORKSPACE_BYTES = 64 << 20   # the static workspace of fslbm_init_static
 
 # Exported symbols, in the order include/fslbm.h declares them.
-SYMBOLS = ["fslbm_workspace_bytes", "fslbm_init", "fslbm_step", "fslbm_step_timed",
+SYMBOLS = ["fslbm_workspace_bytes", "fslbm_init", "fslbm_init_static", "fslbm_step",
+           "fslbm_step_timed",
            "fslbm_refill_scheme",
            "fslbm_use_graphs", "fslbm_set_stream", "fslbm_read_fields", "fslbm_diagnostics",
            "fslbm_last_step_stats", "fslbm_adjoint_workspace_bytes", "fslbm_adjoint_forward",
@@ -85,6 +87,7 @@ def lib() -> ctypes.CDLL:
         P, vp = ctypes.POINTER, ctypes.c_void_p
         L.fslbm_workspace_bytes.argtypes = [P(CParams), P(ctypes.c_size_t)]
         L.fslbm_init.argtypes = [P(CParams), vp, ctypes.c_size_t, vp, vp, vp, vp, vp, vp, P(vp)]
+        L.fslbm_init_static.argtypes = [P(CParams), vp, vp, vp, vp, vp, vp, P(vp)]
         L.fslbm_step.argtypes = [vp, ctypes.c_int32]
         L.fslbm_step_timed.argtypes = [vp, ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_double)]
         L.fslbm_refill_scheme.argtypes = [vp, ctypes.c_int32]
@@ -102,7 +105,8 @@ def lib() -> ctypes.CDLL:
         L.fslbm_last_error.restype = ctypes.c_char_p
         L.fslbm_destroy.argtypes = [vp]
         L.fslbm_destroy.restype = None
-        for name in ("fslbm_workspace_bytes", "fslbm_init", "fslbm_step", "fslbm_step_timed",
+        for name in ("fslbm_workspace_bytes", "fslbm_init", "fslbm_init_static", "fslbm_step",
+                     "fslbm_step_timed",
                      "fslbm_refill_scheme",
                      "fslbm_use_graphs", "fslbm_set_stream", "fslbm_read_fields",
                      "fslbm_diagnostics", "fslbm_adjoint_workspace_bytes",
@@ -186,11 +190,13 @@ class Simulation:
 
     flags [B,N] uint8, phi [B,N], rho [B,N], u [B,3,N] (or pdf [B,19,N] and
     optionally mass [B,N]) are the canonical initial fields (any array type;
-    copied to the device).
+    copied to the device).  static_workspace=True creates the context with
+    fslbm_init_static (the library's own static device workspace, no
+    workspace tensor; one such context per device at a time).
     """
 
     def __init__(self, params: Params, flags, phi, rho=None, u=None, pdf=None, mass=None,
-                 device="cuda", stream=None):
+                 device="cuda", stream=None, static_workspace: bool = False):
         self.params = params
         self.device = torch.device(device)
         B, N = params.batch, params.N
@@ -198,9 +204,12 @@ class Simulation:
         cp, keep = params.to_c(ctypes.c_void_p(self._stream.cuda_stream))
         nbytes = ctypes.c_size_t()
         _check(lib().fslbm_workspace_bytes(ctypes.byref(cp), ctypes.byref(nbytes)))
-        self.workspace = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
-        base = self.workspace.data_ptr()
-        self._ws_ptr = (base + 255) & ~255
+        if static_workspace:
+            self.workspace = None
+        else:
+            self.workspace = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
+            base = self.workspace.data_ptr()
+            self._ws_ptr = (base + 255) & ~255
         f = _dev(flags, torch.uint8, self.device).reshape(B, N)
         ph = _dev(phi, torch.float64, self.device).reshape(B, N)
         r = _dev(rho, torch.float64, self.device).reshape(B, N) if rho is not None else None
@@ -209,10 +218,14 @@ class Simulation:
         ms = _dev(mass, torch.float64, self.device).reshape(B, N) if mass is not None else None
         ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
         ctx = ctypes.c_void_p()
-        with torch.cuda.stream(self._stream):
-            st = lib().fslbm_init(ctypes.byref(cp), ctypes.c_void_p(self._ws_ptr),
-                                  nbytes.value, ptr(f), ptr(ph), ptr(r), ptr(uu), ptr(pd),
-                                  ptr(ms), ctypes.byref(ctx))
+        with torch.cuda.device(self.device), torch.cuda.stream(self._stream):
+            if static_workspace:
+                st = lib().fslbm_init_static(ctypes.byref(cp), ptr(f), ptr(ph), ptr(r), ptr(uu),
+                                             ptr(pd), ptr(ms), ctypes.byref(ctx))
+            else:
+                st = lib().fslbm_init(ctypes.byref(cp), ctypes.c_void_p(self._ws_ptr),
+                                      nbytes.value, ptr(f), ptr(ph), ptr(r), ptr(uu), ptr(pd),
+                                      ptr(ms), ctypes.byref(ctx))
         _check(st, None)
         self._ctx = ctx
         self.steps_done = 0
