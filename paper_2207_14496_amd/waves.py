@@ -84,7 +84,11 @@ def peaks(t, a):
 
 
 def log_decrements(t, a):
-    """delta = ln(|a*(t*)| / |a*(t* + T*)|) between peaks one period apart,
-    from the peak that ends the first period on; returns [(t*, delta)]."""
+    """delta = ln(a*(t*) / a*(t* + T*)) between consecutive positive maxima
+    (Sec. 4.1, decrement equation), the start a*(0) = 1 counting as the first
+    positive maximum; each value is labelled with the time of the later
+    maximum of its pair.  Returns [(t*, delta)]."""
     tp, ap = peaks(t, a)
-    return [(float(tp[j]), float(np.log(abs(ap[j]) / abs(ap[j + 2])))) for j in range(2, len(ap) - 2)]
+    pos = [(x, y) for x, y in zip(tp, ap) if y > 0]
+    return [(float(pos[j + 1][0]), float(np.log(pos[j][1] / pos[j + 1][1])))
+            for j in range(len(pos) - 1)]

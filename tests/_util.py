@@ -53,3 +53,37 @@ def check_topology(st: oracle.State, p: oracle.Params):
     assert np.all(st.phi[fl == LIQ] == 1.0)
     assert np.all(st.phi[fl == GAS] == 0.0)
     assert np.all(st.m[fl != IFC] == 0.0)
+
+
+def before_conversions(p: oracle.Params, st: oracle.State) -> oracle.State:
+    """The state one step on with conversions switched off (eps_phi so large
+    that no fill level crosses it): stream, collide and mass exchange are those
+    of the real step, so its phi, m and f* are the values the conversion rules
+    see."""
+    q = oracle.Params(**{**p.__dict__, "eps_phi": 1e9})
+    return oracle.step(q, st.copy(), 1)
+
+
+def dilate(mask: np.ndarray, p, radius: int) -> np.ndarray:
+    """Cells within Chebyshev distance `radius` of a cell in mask (periodic
+    axes wrap, walls cut)."""
+    return _window(mask.astype(np.float64), p, radius, np.max) > 0
+
+
+def window_max(v: np.ndarray, p, radius: int) -> np.ndarray:
+    """Max of v over the (2 radius + 1)^3 window of every cell (periodic axes
+    wrap; beyond a wall counts as 0)."""
+    return _window(v, p, radius, np.max)
+
+
+def _window(v, p, r, red):
+    a = v.reshape(p.nz, p.ny, p.nx)
+    pads = [(r, r)] * 3
+    for axis, per in ((0, p.periodic[2]), (1, p.periodic[1]), (2, p.periodic[0])):
+        mode = "wrap" if per else "constant"
+        pw = [(0, 0)] * 3
+        pw[axis] = (r, r)
+        a = np.pad(a, pw, mode=mode)
+    from numpy.lib.stride_tricks import sliding_window_view
+    w = sliding_window_view(a, (2 * r + 1,) * 3)
+    return red(w, axis=(3, 4, 5)).reshape(-1)

@@ -1,10 +1,13 @@
 """The gravity-wave monitor (no GPU) and the values the paper prints for it.
 
-Pins: on an exactly damped cosine the monitor returns T*/2 = pi and the
-decrement it was built with; the paper's printed analytic series (Sec. 4.1)
-equals the closed forms T*/2 = pi and delta = 2 nu k^2 T = 0.016 pi^3 (for
-a0 = 0.01 L and Re = 10) to float32 precision; the setup reproduces g = 6.85e-6
-at L = 200 and the stated Reynolds number."""
+Pins: on an exactly damped cosine the monitor returns T*/2 = pi and, from the
+second pair of positive maxima on, the decrement it was built with, and for
+the first pair (the start and the first maximum) its closed form; the paper's
+printed analytic series (Sec. 4.1) equals the closed forms T*/2 = pi and
+delta = 2 nu k^2 T = 0.016 pi^3 (for a0 = 0.01 L and Re = 10) to float32
+precision; the paper's printed per-scheme decrements show what the reading of
+the decrement's labels implies; the setup reproduces g = 6.85e-6 at L = 200
+and the stated Reynolds number."""
 import json
 import os
 
@@ -18,12 +21,40 @@ GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "gravity
 def test_monitor_on_an_exact_damped_cosine():
     t = np.linspace(0.0, 40.0, 40001)
     delta = 0.4961004
-    a = np.exp(-delta / (2 * np.pi) * t) * np.cos(t)
+    gam = delta / (2 * np.pi)
+    a = np.exp(-gam * t) * np.cos(t)
     hp = waves.half_periods(t, a)
     assert np.allclose(hp[:6], np.pi, rtol=0, atol=1e-6)
     ld = waves.log_decrements(t, a)
-    # the damped maxima sit slightly before the cosine's (tan t = -delta / 2 pi)
-    assert abs(ld[0][0] - (2 * np.pi - np.arctan(delta / (2 * np.pi)))) < 1e-3 and all(abs(d - delta) < 1e-7 for _, d in ld[:5])
+    # the damped maxima sit slightly before the cosine's (tan t = -gamma); the
+    # first pair is the start a*(0) = 1 and the first maximum t1, so
+    # delta_1 = gamma t1 + ln(1 + gamma^2) / 2, and every later pair is one
+    # period apart: delta
+    t1 = 2 * np.pi - np.arctan(gam)
+    assert abs(ld[0][0] - t1) < 1e-3
+    assert abs(ld[0][1] - (gam * t1 + 0.5 * np.log1p(gam * gam))) < 1e-7
+    assert all(abs(x - (t1 + 2 * np.pi * k)) < 1e-3 for k, (x, _) in enumerate(ld[:5]))
+    assert all(abs(d - delta) < 1e-7 for _, d in ld[1:5])
+
+
+def test_printed_scheme_decrements_match_the_later_label_reading():
+    """The paper notes that AVG overestimates the wave's first positive
+    amplitude a1 (the maximum near t* = 2 pi).  With each decrement labelled at
+    the later maximum of its pair and the start as the first maximum,
+    delta_1 = ln(1 / a1) falls and delta_2 = ln(a1 / a2) rises when a1 is too
+    large; the printed AVG series has the smallest delta_1 and the largest
+    delta_2 of the four schemes it prints.  (Labelled at the earlier maximum,
+    delta_1 = ln(a1 / a2) would rise instead.)"""
+    sch = GOLD["schemes_L800"]
+    first = {k: v["log_decrement"][0][1] for k, v in sch.items() if v.get("log_decrement")}
+    second = {k: v["log_decrement"][1][1] for k, v in sch.items() if v.get("log_decrement")}
+    assert set(first) == {"EQ", "EQ+NEQ", "GEQ", "AVG"}
+    assert min(first, key=first.get) == "AVG" and max(second, key=second.get) == "AVG"
+    # the labels sit near the maxima one and two periods in
+    for v in sch.values():
+        if v.get("log_decrement"):
+            assert abs(v["log_decrement"][0][0] - 2 * np.pi) < 0.1
+            assert abs(v["log_decrement"][1][0] - 4 * np.pi) < 0.2
 
 
 def test_printed_analytic_values_are_the_closed_forms():
