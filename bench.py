@@ -19,6 +19,10 @@ roofline   the bulk stream-collide kernel: algorithmic bytes per launch (per
            source is on record.
 cpu_baseline  the FP64 CPU oracle (single thread) on a bounded sample of the
            same workload.
+standing_wave_cpu  the 64 x 128 standing wave (SRT omega = 1.8, g = 1e-5, EQ,
+           FP64), 1000 steps: the oracle's CPU seconds (single thread) next to
+           the GPU's seconds for the same 1000 steps, and how far the two
+           final states differ.
 variants   other storage types, the dense pool-wave case (83% fluid), and the
            reduced-precision error against the FP64 run.
 wave_frequency  the Sec. 4.1 gravity wave at L = 400 in every storage type.
@@ -147,6 +151,40 @@ def cpu_baseline(setup, target_s=20.0):
                       f"host nproc={os.cpu_count()})"}
 
 
+def standing_wave_cpu(fslbm, setups, torch, steps=1000):
+    """The 64 x 128 standing wave (FP64, SRT, EQ) for `steps` steps: the oracle
+    as it stands (single thread, CPU seconds) and the GPU for the same steps
+    (one call, graph replay), and the difference of the two final states."""
+    sys.path.insert(0, ROOT)
+    import numpy as np
+    import oracle
+    s = setups.config("standing-wave-64")
+    p = oracle.Params(s.nx, s.ny, s.nz, tuple(s.periodic), s.collision, s.refill, s.omega,
+                      s.trt_lambda, tuple(s.g), s.sigma, s.p_volume, s.eps_phi)
+    st = oracle.init_state(p, s.flags, s.phi, s.rho, s.u)
+    t0 = time.perf_counter()
+    oracle.step(p, st, steps)
+    cpu_s = time.perf_counter() - t0
+    sim = fslbm.from_setup(s, storage=fslbm.F64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    gpu_s = time.perf_counter() - t0
+    got = {k: v.cpu().numpy()[0] for k, v in sim.read(("flags", "pdf", "mass", "phi")).items()}
+    sim.close()
+    fluid = st.flags != 4
+    rec = {"workload": f"standing wave {s.nx}x{s.ny}x{s.nz} SRT omega={s.omega} g={abs(s.g[1]):g} "
+                       f"EQ, FP64", "steps": steps, "cells": s.N,
+           "cpu_seconds": round(cpu_s, 3), "cpu_cores": 1, "cpu_kind": "oracle",
+           "host_nproc": os.cpu_count(), "gpu_seconds": round(gpu_s, 4),
+           "flags_equal": bool(np.array_equal(got["flags"], st.flags)),
+           "max_abs_pdf_diff": float(np.abs(got["pdf"][:, fluid] - st.f[:, fluid]).max()),
+           "max_abs_phi_diff": float(np.abs(got["phi"] - st.phi).max())}
+    log(f"standing wave {steps} steps: oracle {cpu_s:.2f} s (1 thread), GPU {gpu_s * 1e3:.1f} ms")
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -247,6 +285,7 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
         result["cpu_baseline"] = cpu_baseline(setup)
+        result["standing_wave_cpu"] = standing_wave_cpu(fslbm, setups, torch)
     print(json.dumps(result), flush=True)
 
 
@@ -548,7 +587,9 @@ def variants(fslbm, setups, torch, args):
                    "mlups_fluid": round(r["fluid"] * ks / (r["ms"] * 1e-3) / 1e6, 1),
                    "mlups_domain": round(setup.N * ks / (r["ms"] * 1e-3) / 1e6, 1),
                    "ms_per_step": round(r["ms"] / ks, 5), "bulk_gbs": rl["achieved"],
-                   "bulk_frac": rl["frac"], "bulk_kernel_ms": rl["kernel_avg_ms"]}
+                   "bulk_frac": rl["frac"], "bulk_kernel_ms": rl["kernel_avg_ms"],
+                   "bulk_algorithmic_bytes": rl["algorithmic_bytes_per_launch"],
+                   "bulk_traffic_bytes": rl["traffic"]}
             f = r["sim"].read(("phi", "flags"))
             phi = f["phi"][0]
             d = r["d2"]

@@ -55,7 +55,7 @@ bool make_layout(const fslbm_params &p, Layout &L) {
     L.cnt = take(C_COUNT * 4);
     L.nif = take(size_t(2 * p.batch) * ND_SHARDS * 32 * 4);
     L.res = take(size_t(2 * p.batch) * 8);
-    L.omega = take(size_t(p.batch) * 8);
+    L.omega = take(size_t(p.batch) * 16);   // omega (omega+) [B], then TRT omega- [B]
     L.grav = take(size_t(p.batch) * 24);
     L.diag_d = take(size_t(p.batch) * DIAG_BLOCKS * 2 * 8);
     L.diag_i = take(size_t(p.batch) * DIAG_BLOCKS * 4 * 8);
@@ -387,6 +387,8 @@ StepArgs make_args(fslbm_ctx *c, int parity) {
     a.normal = surf ? at<double>(c, c->L.normal) : nullptr;
     a.band = surf ? at<uint32_t>(c, c->L.band) : nullptr;
     a.omega = at<double>(c, c->L.omega);
+    a.omega_m = a.omega + p.batch;
+    a.pdf_off32 = (long long)p.nx * p.ny * p.nz * Q * (long long)storage_bytes(p.storage) < (1LL << 32) ? 1 : 0;
     a.grav = at<double>(c, c->L.grav);
     a.trt_lambda = p.trt_lambda;
     // 2 C_S^2 / c_s^4 with c_s^2 = 1/3
@@ -632,14 +634,16 @@ fslbm_status fslbm_init(const fslbm_params *params, void *workspace, size_t byte
     c->ws = static_cast<char *>(workspace);
     c->stream = static_cast<hipStream_t>(params->stream);
     const int B = params->batch;
-    c->omega_h.resize(B);
+    c->omega_h.resize(2 * B);
     c->grav_h.resize(3 * B);
     for (int b = 0; b < B; ++b) {
         c->omega_h[b] = params->omega_b ? params->omega_b[b] : params->omega;
+        // TRT: (1/omega+ - 1/2)(1/omega- - 1/2) = Lambda
+        c->omega_h[B + b] = 1.0 / (0.5 + params->trt_lambda / (1.0 / c->omega_h[b] - 0.5));
         for (int k = 0; k < 3; ++k)
             c->grav_h[3 * b + k] = params->gravity_b ? params->gravity_b[3 * b + k] : params->gravity[k];
     }
-    bool ok = hip_ok(c, hipMemcpyAsync(at<double>(c, c->L.omega), c->omega_h.data(), 8 * B,
+    bool ok = hip_ok(c, hipMemcpyAsync(at<double>(c, c->L.omega), c->omega_h.data(), 16 * B,
                                        hipMemcpyHostToDevice, c->stream), "hipMemcpy(omega)") &&
               hip_ok(c, hipMemcpyAsync(at<double>(c, c->L.grav), c->grav_h.data(), 24 * B,
                                        hipMemcpyHostToDevice, c->stream), "hipMemcpy(gravity)");

@@ -47,15 +47,20 @@ enum : uint8_t {
 enum Storage { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_BF16 = 3 };
 
 template <int S> struct Codec;
+// decode / encode convert one stored value; load / store do it through memory.
 template <> struct Codec<ST_F64> {
     using T = double;      // arithmetic type
     using M = double;      // memory type
+    __device__ static T decode(M m) { return m; }
+    __device__ static M encode(T v) { return v; }
     __device__ static T load(const M *p) { return *p; }
     __device__ static void store(M *p, T v) { *p = v; }
 };
 template <> struct Codec<ST_F32> {
     using T = float;
     using M = float;
+    __device__ static T decode(M m) { return m; }
+    __device__ static M encode(T v) { return v; }
     __device__ static T load(const M *p) { return *p; }
     __device__ static void store(M *p, T v) { *p = v; }
 };
@@ -63,19 +68,23 @@ template <> struct Codec<ST_F16> {
     using T = float;
     using M = _Float16;
     static constexpr float S = 1024.0f, IS = 1.0f / 1024.0f;  // exact powers of two
-    __device__ static T load(const M *p) { return float(*p) * IS; }
-    __device__ static void store(M *p, T v) { *p = (_Float16)(v * S); }
+    __device__ static T decode(M m) { return float(m) * IS; }
+    __device__ static M encode(T v) { return (_Float16)(v * S); }
+    __device__ static T load(const M *p) { return decode(*p); }
+    __device__ static void store(M *p, T v) { *p = encode(v); }
 };
 template <> struct Codec<ST_BF16> {
     using T = float;
     using M = uint16_t;
-    __device__ static T load(const M *p) { return __uint_as_float(uint32_t(*p) << 16); }
-    __device__ static void store(M *p, T v) {
+    __device__ static T decode(M m) { return __uint_as_float(uint32_t(m) << 16); }
+    __device__ static M encode(T v) {
         // round to nearest even on the upper 16 bits (finite inputs)
         uint32_t u = __float_as_uint(v);
         u += 0x7FFFu + ((u >> 16) & 1u);
-        *p = uint16_t(u >> 16);
+        return uint16_t(u >> 16);
     }
+    __device__ static T load(const M *p) { return decode(*p); }
+    __device__ static void store(M *p, T v) { *p = encode(v); }
 };
 
 // A value as it reads back after a store in storage type ST.
@@ -277,6 +286,7 @@ struct StepArgs {
     double *normal;        // [3][BN] unit normals on the band (sigma != 0)
     uint32_t *band;        // [ceil(BN/32)] band membership bits (sigma != 0)
     const double *omega;   // [B]
+    const double *omega_m; // [B] TRT omega- (from omega+ and trt_lambda)
     const double *grav;    // [B][3]
     double trt_lambda;
     double les_k;          // Smagorinsky: 2 C_S^2 / c_s^4 (0 = no turbulence model)
@@ -291,6 +301,7 @@ struct StepArgs {
     int32_t *tiles;        // tiles (TILE consecutive cells) that ever held fluid
     uint32_t *tile_bits;   // membership bits of that list
     int bulk_grid;         // workgroups of the bulk kernel (its wavefronts stride over the tiles)
+    int pdf_off32;         // 1 if one domain's populations take less than 4 GiB (32-bit byte offsets)
     int32_t *cnt;          // device counters, see Counter
     int32_t *nif_dom;      // sharded interface cells per domain (see ND_SHARDS): counted by
                            // the interface kernel, then corrected by the step's conversions

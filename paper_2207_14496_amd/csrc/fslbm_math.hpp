@@ -7,18 +7,37 @@
 
 namespace fslbm {
 
+// c_i . v over the nonzero components of c_i (each +-1), so that a direction
+// with zero components costs no multiplication: without fast-math a product
+// 0 * v cannot be folded away (v may be NaN or -0).  The rest direction gives 0.
+template <typename T>
+__device__ __forceinline__ T cdot(int i, T vx, T vy, T vz) {
+    T s = T(0);
+    bool any = false;
+    auto add = [&](int c, T v) {
+        if (c == 0) return;
+        const T t = c > 0 ? v : -v;
+        s = any ? s + t : t;
+        any = true;
+    };
+    add(cx(i), vx);
+    add(cy(i), vy);
+    add(cz(i), vz);
+    return s;
+}
+
 // Equilibrium (Sec. 2.1) minus its weight: f_eq_i(rho,u) - w_i with c_s^2 = 1/3.
 template <typename T>
 __device__ __forceinline__ T feq_shift(int i, T rho, T drho, T ux, T uy, T uz, T uu) {
-    T uc = T(cx(i)) * ux + T(cy(i)) * uy + T(cz(i)) * uz;
+    T uc = cdot<T>(i, ux, uy, uz);
     return wgt<T>(i) * (drho + rho * (T(3) * uc + T(4.5) * uc * uc - T(1.5) * uu));
 }
 
 // Guo forcing term without its (1 - omega/2) prefactor (Sec. 2.1).
 template <typename T>
 __device__ __forceinline__ T guo_hat(int i, T ux, T uy, T uz, T Fx, T Fy, T Fz) {
-    T uc = T(cx(i)) * ux + T(cy(i)) * uy + T(cz(i)) * uz;
-    T cF = T(cx(i)) * Fx + T(cy(i)) * Fy + T(cz(i)) * Fz;
+    T uc = cdot<T>(i, ux, uy, uz);
+    T cF = cdot<T>(i, Fx, Fy, Fz);
     T uF = ux * Fx + uy * Fy + uz * Fz;
     return wgt<T>(i) * (T(3) * (cF - uF) + T(9) * uc * cF);
 }
@@ -67,31 +86,49 @@ __device__ __forceinline__ void collide(T (&d)[Q], T om, T omm, T gx, T gy, T gz
         om = T(1) / tau;
         if (COLL & 1) omm = T(1) / (T(0.5) + lambda / (tau - T(0.5)));
     }
-    if ((COLL & 1) == 0) {
-        T pf = T(1) - T(0.5) * om;
+    // Per pair (i, opp(i)) the equilibrium and the Guo term split into a part
+    // even in c_i and one odd in c_i; with uc = c_i.u and cF = c_i.F:
+    //   f_eq - w = w (A + 4.5 rho uc^2) +- 3 w rho uc,   A = (rho - 1) - 1.5 rho u.u
+    //   F^      = w (9 uc cF - 3 u.F)   +- 3 w cF
+    // The relaxation then needs, per weight class w (faces 1/18, edges 1/36),
+    //   even:  om (f_eq - w)_even + pf+ F^_even = K0 + K1 uc^2 + K2 uc cF
+    //   odd:   om' (f_eq - w)_odd + pf' F^_odd  = K3 uc + K4 cF
+    // (om' = om, pf' = pf+ for SRT; omega-, pf- for TRT), so each pair costs
+    // one uc, one cF and a handful of fused multiply-adds.
+    const T uF = ux * Fx + uy * Fy + uz * Fz;
+    const T A = drho - T(1.5) * rho * uu;
+    const T pfp = T(1) - T(0.5) * om;
+    const T omo = (COLL & 1) ? omm : om;
+    const T pfo = T(1) - T(0.5) * omo;
+    {
+        const T w0 = wgt<T>(0);
+        d[0] = d[0] - om * (d[0] - w0 * A) - pfp * (w0 * (T(3) * uF));
+    }
+    T K0[2], K1[2], K2[2], K3[2], K4[2];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            T e = feq_shift<T>(i, rho, drho, ux, uy, uz, uu);
-            d[i] = d[i] - om * (d[i] - e) + pf * guo_hat<T>(i, ux, uy, uz, Fx, Fy, Fz);
-        }
-    } else {
-        T pfp = T(1) - T(0.5) * om, pfm = T(1) - T(0.5) * omm;
-        {
-            T e = feq_shift<T>(0, rho, drho, ux, uy, uz, uu);
-            d[0] = d[0] - om * (d[0] - e) + pfp * guo_hat<T>(0, ux, uy, uz, Fx, Fy, Fz);
-        }
+    for (int cl = 0; cl < 2; ++cl) {
+        const T w = cl == 0 ? wgt<T>(1) : wgt<T>(7);
+        K0[cl] = om * (w * A) - pfp * (w * (T(3) * uF));
+        K1[cl] = om * (w * (T(4.5) * rho));
+        K2[cl] = pfp * (T(9) * w);
+        K3[cl] = omo * (w * (T(3) * rho));
+        K4[cl] = pfo * (T(3) * w);
+    }
+    const T keep = T(1) - om;
+    const T hp = T(0.5) * om, hm = T(0.5) * omm;
 #pragma unroll
-        for (int i = 1; i < Q; i += 2) {
-            const int k = i + 1;
-            T ei = feq_shift<T>(i, rho, drho, ux, uy, uz, uu);
-            T ek = feq_shift<T>(k, rho, drho, ux, uy, uz, uu);
-            T Fi = guo_hat<T>(i, ux, uy, uz, Fx, Fy, Fz);
-            T Fk = guo_hat<T>(k, ux, uy, uz, Fx, Fy, Fz);
-            T fs = T(0.5) * (d[i] + d[k]), fa = T(0.5) * (d[i] - d[k]);
-            T es = T(0.5) * (ei + ek), ea = T(0.5) * (ei - ek);
-            T Fs = T(0.5) * (Fi + Fk), Fa = T(0.5) * (Fi - Fk);
-            T rs = -om * (fs - es) + pfp * Fs;
-            T ra = -omm * (fa - ea) + pfm * Fa;
+    for (int i = 1; i < Q; i += 2) {
+        const int k = i + 1, cl = i <= 6 ? 0 : 1;
+        const T uc = cdot<T>(i, ux, uy, uz), cF = cdot<T>(i, Fx, Fy, Fz);
+        const T P = K0[cl] + K1[cl] * (uc * uc) + K2[cl] * (uc * cF);   // even part
+        const T M = K3[cl] * uc + K4[cl] * cF;                           // odd part
+        if ((COLL & 1) == 0) {
+            d[i] = keep * d[i] + (P + M);
+            d[k] = keep * d[k] + (P - M);
+        } else {
+            // symmetric and antisymmetric relaxation of (d_i + d_k)/2, (d_i - d_k)/2
+            const T rs = P - hp * (d[i] + d[k]);
+            const T ra = M - hm * (d[i] - d[k]);
             d[i] = d[i] + rs + ra;
             d[k] = d[k] + rs - ra;
         }

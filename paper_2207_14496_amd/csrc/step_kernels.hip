@@ -427,11 +427,7 @@ __device__ __forceinline__ bool update_cell(const StepArgs &a, const long long g
 
     const double *gr = a.grav + 3 * c.b;
     const T om = T(a.omega[c.b]);
-    T omm = om;
-    if (COLL & 1) {
-        double op = a.omega[c.b];
-        omm = T(1.0 / (0.5 + a.trt_lambda / (1.0 / op - 0.5)));
-    }
+    const T omm = (COLL & 1) ? T(a.omega_m[c.b]) : om;
     collide<T, COLL>(d, om, omm, T(gr[0]), T(gr[1]), T(gr[2]), T(a.les_k), T(a.trt_lambda));
 
     C::store(base + n, d[0]);
@@ -465,14 +461,105 @@ __device__ __forceinline__ bool update_cell(const StepArgs &a, const long long g
     return marked;
 }
 
+// Global-memory pointer (address space 1), so that accesses through it are
+// global, not flat, instructions.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T *;
+
+// A global pointer that is the same on every lane of the wavefront, held in
+// scalar registers and opaque to the compiler's address folding: an access at
+// it plus a 32-bit lane byte offset is then one global instruction with a
+// scalar base and a vector offset, with no per-lane 64-bit address arithmetic.
+template <typename T>
+__device__ __forceinline__ gptr<T> wave_ptr(T *p) {
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(v));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(v >> 32));
+    return (gptr<T>)((uint64_t(hi) << 32) | uint64_t(lo));
+}
+template <typename T>
+__device__ __forceinline__ gptr<T> at_bytes(gptr<T> base, uint32_t off) {
+    return (gptr<T>)((__attribute__((address_space(1))) char *)base + off);
+}
+
+// Update of the liquid cells of a plain tile (see tile_is_plain; lane l takes
+// cell n0 + l of domain b): every lane reads and writes at fixed offsets from
+// its own cell, so slot (d, n + delta) is base_d[n] with a per-direction base
+// that is the same for the whole wavefront.  All accesses share one 32-bit
+// lane byte offset (the domain's populations take less than 4 GiB: pdf_off32)
+// and the domain's omega and g are scalar loads.  Only liquid lanes load and
+// store.  (Issuing the population loads of all lanes together with the flag
+// loads, so that no load waits for the cell types, was measured slower on
+// partly liquid tiles and no faster on full ones.)  Returns the lane's cell
+// type (as type_after reads it).  Arithmetic as update_cell.
+template <int ST, int COLL, int PAR>
+__device__ __forceinline__ uint8_t update_plain_tile(const StepArgs &a, const int b, const uint32_t n0) {
+    using C = Codec<ST>;
+    using T = typename C::T;
+    using Mem = typename C::M;
+    const Geom &g = a.g;
+    const long long N = g.N;
+    const uint32_t n = n0 + uint32_t(__lane_id());
+    // cell offset of the neighbour x + c_i (no wall and no periodic wrap here)
+    auto delta = [&](int i) -> long long {
+        return (long long)cx(i) + (long long)cy(i) * g.nx + (long long)cz(i) * g.nx * g.ny;
+    };
+    Mem *pb = static_cast<Mem *>(a.pdf) + (long long)b * Q * N;
+    const uint32_t off = n * uint32_t(sizeof(Mem));
+    const uint8_t fl = *at_bytes(wave_ptr(a.flags + (long long)b * N), n);
+    const uint8_t ty = type_after(fl);
+    if (ty != F_LIQ) return ty;
+    T d[Q];
+    {
+        d[0] = C::decode(*at_bytes(wave_ptr(pb), off));
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            // PAR 0 pulls f*_i(x - c_i) from slot (opp(i), x - c_i); PAR 1 reads (i, x)
+            Mem *bi = PAR == 0 ? pb + (long long)opp(i) * N - delta(i) : pb + (long long)i * N;
+            d[i] = C::decode(*at_bytes(wave_ptr(bi), off));
+        }
+    }
+    const double *gr = a.grav + 3 * b;
+    const T om = T(a.omega[b]);
+    const T omm = (COLL & 1) ? T(a.omega_m[b]) : om;
+    collide<T, COLL>(d, om, omm, T(gr[0]), T(gr[1]), T(gr[2]), T(a.les_k), T(a.trt_lambda));
+    *at_bytes(wave_ptr(pb), off) = C::encode(d[0]);
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        // PAR 0 pushes into (i, x + c_i); PAR 1 writes (opp(i), x)
+        Mem *bi = PAR == 0 ? pb + (long long)i * N + delta(i) : pb + (long long)opp(i) * N;
+        *at_bytes(wave_ptr(bi), off) = C::encode(d[i]);
+    }
+    return ty;
+}
+
+// A tile (64 consecutive cells from gid0) is plain when every lane's update
+// reads and writes only slots at fixed offsets from its own cell: for the
+// layout A -> B step (PAR 0) the tile lies inside one row with no cell on a
+// face of the box (so no wall and no periodic wrap among the neighbours); for
+// the layout B -> A step (PAR 1, local slots only) it lies inside one domain.
+template <int PAR>
+__device__ __forceinline__ bool tile_is_plain(const StepArgs &a, uint32_t gid0, int &b, uint32_t &n0) {
+    const Geom &g = a.g;
+    if (!a.pdf_off32) return false;
+    const uint32_t bb = g.dN.div(gid0);
+    n0 = gid0 - bb * uint32_t(g.N);
+    b = int(bb);
+    if (PAR == 1) return (long long)n0 + TILE <= g.N;
+    const uint32_t r = g.dx.div(n0);
+    const uint32_t z = g.dy.div(r);
+    const int x0 = int(n0 - r * uint32_t(g.nx)), y0 = int(r - z * uint32_t(g.ny));
+    return x0 >= 1 && x0 + TILE <= g.nx - 1 && y0 >= 1 && y0 + 1 < g.ny && int(z) >= 1 && int(z) + 1 < g.nz;
+}
+
 // Bulk kernel: one thread per cell, one wavefront per tile of 64 consecutive
 // cells (x fastest, so every PDF access of a wavefront is a contiguous row
 // segment).  Only tiles that ever held fluid are listed; the wavefronts stride
 // over that list, so a mostly empty domain does not pay for its gas, and a
 // wavefront never loads a row segment without fluid.  Liquid cells get the full
-// stream-collide update.  Interface cells are listed for k_interface in tile
-// order, so the list kernels of the step read neighbouring cells from
-// neighbouring lanes.
+// stream-collide update (plain tiles through update_liquid_plain).  Interface
+// cells are listed for k_interface in tile order, so the list kernels of the
+// step read neighbouring cells from neighbouring lanes.
 // Cell types are read through type_after: with the last step's excess-mass
 // work running in the same grid, a new interface cell may still carry its
 // gas-typed flag while this kernel reads it.
@@ -489,18 +576,36 @@ __device__ __forceinline__ void bulk_part(const StepArgs &a, const int wg, const
     const int32_t ntiles = int32_t(tile_count(a.g.BN));
     const int32_t nt = min(a.cnt[C_TILES], ntiles);
     const int32_t nw = int32_t(blockDim.x >> 6);
-    for (int32_t k = wg * nw + int32_t(threadIdx.x >> 6); k < nt; k += nwg * nw) {
-        const long long gid = ((long long)a.tiles[k] << TILE_SHIFT) + __lane_id();
-        const bool valid = gid < a.g.BN;
-        const uint8_t fl = valid ? a.flags[gid] : uint8_t(0);
-        const uint8_t ty = type_after(fl);
-        if (ty == F_LIQ) update_cell<ST, COLL, PAR, false>(a, gid, fl);
+    // the wavefront's index is the same on all its lanes; say so, so that the
+    // tile index and everything derived from it live in scalar registers
+    const int32_t wave = __builtin_amdgcn_readfirstlane(int32_t(threadIdx.x >> 6));
+    for (int32_t k = wg * nw + wave; k < nt; k += nwg * nw) {
+        const int32_t tile = __builtin_amdgcn_readfirstlane(a.tiles[k]);
+        const long long gid = ((long long)tile << TILE_SHIFT) + __lane_id();
+        int b;
+        uint32_t n0;
+        uint8_t ty;
+        if (tile_is_plain<PAR>(a, uint32_t(tile) << TILE_SHIFT, b, n0)) {
+            ty = update_plain_tile<ST, COLL, PAR>(a, b, n0);
+        } else {
+            const bool valid = gid < a.g.BN;
+            const uint8_t fl = valid ? a.flags[gid] : uint8_t(0);
+            ty = type_after(fl);
+            if (ty == F_LIQ) update_cell<ST, COLL, PAR, false>(a, gid, fl);
+        }
         slist_append(a.list_if, ty == F_IF, int32_t(gid), a.cnt + C_ERR);
     }
 }
 
+// Two-byte storage moves half the bytes per wavefront of FP32, so it needs
+// more wavefronts in flight to keep HBM busy: at least five per SIMD (measured
+// on the dense pool: 511 -> 444 us per FP16 bulk launch; the same bound makes
+// FP32 slower, 710 -> 724 us, as its register budget then spills).
+template <int ST>
+constexpr int bulk_min_waves() { return ST >= ST_F16 ? 5 : 1; }
+
 template <int ST, int COLL, int PAR>
-__global__ __launch_bounds__(256) void k_stream_collide(StepArgs a) {
+__global__ __launch_bounds__(256, bulk_min_waves<ST>()) void k_stream_collide(StepArgs a) {
     bulk_part<ST, COLL, PAR>(a, int(blockIdx.x), int(gridDim.x));
 }
 
@@ -1011,7 +1116,7 @@ constexpr int EXCESS_WG = 512;
 // cell's slot set is its own).  Its latency-bound chains overlap the
 // bandwidth-bound bulk instead of running as a kernel of their own.
 template <int ST, int COLL, int PAR>
-__global__ __launch_bounds__(256) void k_excess_stream_collide(StepArgs a, StepArgs ae) {
+__global__ __launch_bounds__(256, bulk_min_waves<ST>()) void k_excess_stream_collide(StepArgs a, StepArgs ae) {
     if (blockIdx.x < EXCESS_WG)
         excess_part<ST>(ae, int(blockIdx.x), EXCESS_WG);
     else

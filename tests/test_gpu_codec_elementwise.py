@@ -41,11 +41,13 @@ def _need_gpu():
 
 def _cases():
     out = []
-    s = setups.random_interface_state(64, 24, 16, 4, periodic=(1, 1, 0), g=(0.0, 0.0, -1e-4),
+    # rows of 192 cells: the middle tile of each interior row takes the bulk
+    # kernel's uniform-offset path, the others the general one
+    s = setups.random_interface_state(192, 16, 12, 4, periodic=(1, 1, 0), g=(0.0, 0.0, -1e-4),
                                       collision=1, refill=0)
-    out.append(("random 64x24x16 TRT EQ", s, 0))
-    s = setups.random_interface_state(64, 24, 16, 5, periodic=(1, 1, 1), refill=4)
-    out.append(("random 64x24x16 SRT AVG", s, 0))
+    out.append(("random 192x16x12 TRT EQ", s, 0))
+    s = setups.random_interface_state(192, 16, 12, 5, periodic=(1, 1, 1), refill=4)
+    out.append(("random 192x16x12 SRT AVG", s, 0))
     s = setups.rect_dam_break(40, 6, 24, width=12, height=16, g=2e-4, refill=2)
     out.append(("dam break 40x6x24 TRT GEQ at step 115", s, 115))
     return out

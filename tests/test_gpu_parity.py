@@ -65,6 +65,31 @@ def test_random_states_all_schemes(scheme):
         assert ref.counts is not None
 
 
+@pytest.mark.parametrize("collision,smag", [(0, 0.0), (1, 0.0), (1, 0.15)])
+def test_random_states_wide_rows(collision, smag):
+    """Rows of 192 cells: the tile in the middle of every interior row is
+    updated through the bulk kernel's uniform-offset path in both step
+    parities, the tiles at the row ends and the boundary rows through the
+    general one.  One domain and a batch of two, one step per call and four."""
+    s0 = setups.random_interface_state(192, 12, 10, 40 + collision, periodic=(1, 1, 0),
+                                       g=(0.0, 0.0, -1e-4), collision=collision)
+    s1 = setups.random_interface_state(192, 12, 10, 50 + collision, periodic=(1, 1, 0),
+                                       g=(0.0, 0.0, -1e-4), collision=collision)
+    p = oracle_params(s0, smag_cs=smag)
+    announce(f"wide rows 192x12x10 collision {collision} smagorinsky {smag}")
+    _run_pair(p, oracle_state(s0, p), 3, "wide rows")
+    sts = [oracle_state(s0, p), oracle_state(s1, p)]
+    sim = sim_from_states(p, sts)
+    for k in range(3):
+        sim.step(4)
+        for st in sts:
+            oracle.step(p, st, 4)
+        got = fields_np(sim)
+        for b, st in enumerate(sts):
+            compare(got, b, st, 1e-11, 1e-11, 1e-11, what=f"wide rows batch domain {b} step {4 * (k + 1)}")
+    sim.close()
+
+
 @pytest.mark.parametrize("scheme", range(5))
 def test_dam_break_small_all_schemes(scheme):
     """Small 3-D dam break (TRT, walls): 40 steps of collapse with conversions,
