@@ -299,30 +299,37 @@ __device__ __forceinline__ bool interface_part(const StepArgs &a, const long lon
     for (int i = 1; i < Q; ++i) fn[i] = src[i] >= 0 ? fn[i] : uint8_t(0);
     // mass exchange: the neighbour x + c_i is the source of direction opp(i)
     const int cc = fclass(fl);
-    // fill levels of the interface neighbours, all loads in flight together
-    // (the cell's own where the neighbour is not interface; unused there)
-    double phn[Q];
-#pragma unroll
-    for (int i = 1; i < Q; ++i) {
-        const int o = opp(i);
-        const bool itf = src[o] >= 0 && !(fn[o] & (F_GAS | F_LIQ));
-        phn[i] = a.phi_cur[itf ? cbase + src[o] : gid];
-    }
-    issue_fence();
+    // fill levels of the interface neighbours, loads in flight together (the
+    // cell's own where the neighbour is not interface; unused there); with
+    // FP64 populations in two batches of nine directions, which keeps the
+    // free-slip interface update within 256 registers
+    constexpr int NB = sizeof(T) == 8 ? 2 : 1;
     double dm = 0.0;
 #pragma unroll
-    for (int i = 1; i < Q; ++i) {
-        const int o = opp(i);
-        const uint8_t f = fn[o];
-        // (no wall link; a free-slip path back into this cell exchanges nothing)
-        if (src[o] < 0 || (SLIP && src[o] == c.n) || (f & F_GAS)) continue;
-        const double w = wgt<double>(i);
-        const double fin = w + double(d[o]);    // f*_opp(i)(x + c_i, t)
-        const double fout = w + double(fo[i]);  // f*_i(x, t)
-        if (f & F_LIQ) {
-            dm += fin - fout;
-        } else {
-            dm += 0.5 * (phx + phn[i]) * link_flux(cc, fclass(f), fin, fout);
+    for (int h = 0; h < NB; ++h) {
+        const int i0 = 1 + h * (18 / NB), i1 = 1 + (h + 1) * (18 / NB);
+        double phn[Q];
+#pragma unroll
+        for (int i = i0; i < i1; ++i) {
+            const int o = opp(i);
+            const bool itf = src[o] >= 0 && !(fn[o] & (F_GAS | F_LIQ));
+            phn[i] = a.phi_cur[itf ? cbase + src[o] : gid];
+        }
+        issue_fence();
+#pragma unroll
+        for (int i = i0; i < i1; ++i) {
+            const int o = opp(i);
+            const uint8_t f = fn[o];
+            // (no wall link; a free-slip path back into this cell exchanges nothing)
+            if (src[o] < 0 || (SLIP && src[o] == c.n) || (f & F_GAS)) continue;
+            const double w = wgt<double>(i);
+            const double fin = w + double(d[o]);    // f*_opp(i)(x + c_i, t)
+            const double fout = w + double(fo[i]);  // f*_i(x, t)
+            if (f & F_LIQ) {
+                dm += fin - fout;
+            } else {
+                dm += 0.5 * (phx + phn[i]) * link_flux(cc, fclass(f), fin, fout);
+            }
         }
     }
     // velocity of the cell at the last step from its post-collision populations
@@ -391,34 +398,32 @@ __device__ __forceinline__ bool update_cell(const StepArgs &a, const long long g
         return (Z * g.ny + Y) * g.nx + X;
     };
     constexpr bool SLIPC = (COLL & 4) != 0;   // free-slip walls
+    const uint32_t N32 = uint32_t(N);      // slot offsets fit 32 bits (N * 19 < 2^32)
     // source cell x - c_i of each incoming population (-1 = no-slip wall) and
-    // the direction it was sent in (i, or at a free-slip wall the reflected
-    // direction from the cell the specular path comes from)
-    int src[Q], sdir[Q];
-    src[0] = n;
-    sdir[0] = 0;
-#pragma unroll
-    for (int i = 1; i < Q; ++i) {
-        src[i] = nbl(-cx(i), -cy(i), -cz(i));
-        sdir[i] = i;
-        if (SLIPC && src[i] < 0) {
-            int rx, ry, rz;
-            src[i] = slip_target(g, c.x, c.y, c.z, -cx(i), -cy(i), -cz(i), rx, ry, rz);
-            sdir[i] = dir_index(-rx, -ry, -rz);
-        }
-    }
-
+    // its population: the direction it was sent in is i, or at a free-slip
+    // wall the reflected direction from the cell the specular path comes from
+    // (used at once, so that no per-direction array of it stays live)
+    int src[Q];
     T d[Q];
+    src[0] = n;
     d[0] = C::load(base + n);
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
+        int sc = nbl(-cx(i), -cy(i), -cz(i));
+        int sd = i;
+        if (SLIPC && sc < 0) {
+            int rx, ry, rz;
+            sc = slip_target(g, c.x, c.y, c.z, -cx(i), -cy(i), -cz(i), rx, ry, rz);
+            sd = dir_index(-rx, -ry, -rz);
+        }
+        src[i] = sc;
         if (PAR == 0) {
             // no-slip wall: the redirected f*_opp(i)(x) sits in (i, x); free-slip
-            // wall: f*_sdir(src) sits in (opp(sdir), src) like any layout-A value
-            const uint32_t off = src[i] < 0 ? uint32_t(i * N + n) : uint32_t(opp(sdir[i]) * N + src[i]);
+            // wall: f*_sd(src) sits in (opp(sd), src) like any layout-A value
+            const uint32_t off = sc < 0 ? uint32_t(i) * N32 + uint32_t(n) : uint32_t(opp(sd)) * N32 + uint32_t(sc);
             d[i] = C::load(base + off);
         } else {
-            d[i] = C::load(base + i * N + n);
+            d[i] = C::load(base + uint32_t(i) * N32 + uint32_t(n));
         }
     }
 
@@ -752,6 +757,12 @@ __device__ __forceinline__ void refill_group(const StepArgs &a, const long long 
     // own at a wall or on an idle lane); values of cells that are not valid
     // sources are masked out below, never multiplied in
     const long long qg = cbase + (q >= 0 ? q : c.n);
+    // EQ+NEQ and EXT need the fill-level gradient after streaming at the new
+    // cell; it is taken before the neighbour's populations are loaded, so that
+    // its 26 fill levels and those populations are not live together
+    double nx_ = 0.0, ny_ = 0.0, nz_ = 0.0;
+    if ((SCHEME == 1 || SCHEME == 3) && active)
+        py_gradient(a.g, c, [&](long long k) { return a.phi_next[k]; }, nx_, ny_, nz_);
     const uint8_t fq = a.flags[qg];
     double d[Q];
     load_cell<ST, SLIP>(a, layoutB, decode(a.g, qg), d);
@@ -775,9 +786,6 @@ __device__ __forceinline__ void refill_group(const StepArgs &a, const long long 
     if (SCHEME == 1 || SCHEME == 3) {
         // c^n: the valid direction best aligned with grad(phi) after streaming;
         // scores within rounding of the best tie and the lowest index wins
-        double nx_ = 0.0, ny_ = 0.0, nz_ = 0.0;
-        if (active)
-            py_gradient(a.g, c, [&](long long k) { return a.phi_next[k]; }, nx_, ny_, nz_);
         const double sc = valid ? __dadd_rn(__dadd_rn(__dmul_rn(double(ox), nx_), __dmul_rn(double(oy), ny_)),
                                             __dmul_rn(double(oz), nz_))
                                 : -1e300;
