@@ -71,7 +71,6 @@ bool make_layout(const fslbm_params &p, Layout &L) {
     L.bkept = bub ? take(size_t(BN) * 8) : 0;
     L.bamount = bub ? take(size_t(BN) * 8) : 0;
     L.batm = bub ? take(size_t(BN) * 4) : 0;
-    L.bflag = bub ? take(size_t(bubble_pass_cap(p)) * 4) : 0;
     L.total = off;
     return true;
 }
@@ -722,7 +721,7 @@ fslbm_status fslbm_step(fslbm_ctx *c, int32_t nsteps) {
             if (!hip_ok(c, hipGetLastError(), "step kernel launch")) return c->status;
             c->pending = false;
             ++c->t;
-            if (!bubble_end(c)) return c->status;
+            if (!bubble_end(c, c->stream)) return c->status;
         }
         return FSLBM_OK;
     }

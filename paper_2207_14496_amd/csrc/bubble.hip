@@ -12,13 +12,18 @@
 // (Boyle's law), a merge adds amounts, the parts of a split share one pressure.
 //
 // Labels are global cell indices: every set ends up labelled with its
-// smallest cell index.  They come from passes of label propagation (each cell
-// takes the smallest label around it, then the label of the cell its label
-// names) until a pass changes nothing.  Every pass has its own change flag and
-// returns at once when the pass before it changed nothing, so the host
-// launches a batch of passes (as many as the last labelling took) and reads
-// the flags once.  Per-label sums are double atomics.  The model runs with
-// direct launches between the steps (fslbm_step), for the runs with enclosed gas.
+// smallest cell index.  They come from a union-find over parent pointers that
+// only ever fall and always name a cell of the same set.  A seed pass points
+// every cell at its smallest neighbour of the set; two propagation passes
+// lower each pointer to the smallest label around the cell, then to that
+// label's own label, which shortens the trees; a merge pass joins the two
+// trees of every link (the lock-free linking by atomic minimum of Playne and
+// Hawick, IEEE TPDS 2018, with path halving); a last pass takes each cell's
+// root, the smallest index of its tree, and adds its gas volume to it.  A
+// fixed number of launches, whatever the sets' shapes, and no host
+// synchronisation.  Per-label sums are double atomics.  The model runs with
+// direct launches between the steps (fslbm_step), for the runs with enclosed
+// gas.
 #include <algorithm>
 #include <utility>
 #include <vector>
@@ -52,26 +57,81 @@ __device__ __forceinline__ void wave_add_by_label(int32_t l, double v, double *d
     }
 }
 
-// Every gas and interface cell labelled with its own index, liquid -1; the
-// passes' change flags and the per-label sums of this labelling cleared.
-__global__ __launch_bounds__(BS) void k_bub_seed(StepArgs a, int32_t *lab, int32_t *flags, int nflags,
-                                                 double *z0, double *z1, double *z2, int32_t *z3) {
+// Parent pointers: every gas or interface cell points at the smallest index
+// among itself and its gas or interface D3Q19 neighbours, liquid -1.  The
+// per-label sums of this labelling are cleared where they can be read: V,
+// amount and atm (indexed by this labelling) on its gas and interface cells,
+// kept (indexed by the start labels lab0) on the cells lab0 labels.
+__global__ __launch_bounds__(BS) void k_bub_seed(StepArgs a, int32_t *lab, const int32_t *lab0, double *V,
+                                                 double *kept, double *amount, int32_t *atm) {
     const long long gid = (long long)blockIdx.x * BS + threadIdx.x;
-    for (long long i = gid; i < nflags; i += (long long)gridDim.x * BS) flags[i] = 0;
     if (gid >= a.g.BN) return;
-    lab[gid] = gas_phase(a.flags[gid]) ? int32_t(gid) : -1;
-    if (z0) z0[gid] = 0.0;
-    if (z1) z1[gid] = 0.0;
-    if (z2) z2[gid] = 0.0;
-    if (z3) z3[gid] = 0;
+    if (kept && lab0[gid] >= 0) kept[gid] = 0.0;
+    if (!gas_phase(a.flags[gid])) {
+        lab[gid] = -1;
+        return;
+    }
+    const Cell c = decode(a.g, gid);
+    const long long cb = (long long)c.b * a.g.N;
+    uint8_t fq[Q];
+    int q[Q];
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        q[i] = nb_local(a.g, c.x, c.y, c.z, cx(i), cy(i), cz(i));
+        fq[i] = a.flags[cb + (q[i] >= 0 ? q[i] : c.n)];
+    }
+    int32_t m = int32_t(gid);
+#pragma unroll
+    for (int i = 1; i < Q; ++i)
+        if (q[i] >= 0 && gas_phase(fq[i]) && int32_t(cb + q[i]) < m) m = int32_t(cb + q[i]);
+    lab[gid] = m;
+    if (V) V[gid] = 0.0;
+    if (amount) amount[gid] = 0.0;
+    if (atm) atm[gid] = 0;
 }
 
-// Propagation pass k.  Labels only ever name gas or interface cells of the
-// same set and only fall, so the fixed point is each set's smallest index.
-// A pass after one that changed nothing has nothing to do.
-__global__ __launch_bounds__(BS) void k_bub_pass(StepArgs a, int32_t *lab, int32_t *flags, int k) {
+// Root of x's tree.  Parents are read past the per-CU cache: an older value
+// is only a larger parent of the same set, so it delays nothing but a retry.
+__device__ __forceinline__ int32_t uf_root(int32_t *lab, int32_t x) {
+    int32_t p = __hip_atomic_load(lab + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    while (p != x) {
+        const int32_t gp = __hip_atomic_load(lab + p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (gp == p) return p;
+        // path halving: x now points at its grandparent, an ancestor of the same set
+        atomicMin(lab + x, gp);
+        x = gp;
+        p = __hip_atomic_load(lab + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return x;
+}
+
+// Join the trees of x and y: the larger root is pointed at the smaller one by
+// an atomic minimum.  If that root had meanwhile been given a parent (old), it
+// now points at the smaller root instead, and the join continues with old, so
+// that old's tree is joined as well.  The larger of the two roots falls with
+// every retry, so the loop ends.
+__device__ __forceinline__ void uf_join(int32_t *lab, int32_t x, int32_t y) {
+    for (;;) {
+        x = uf_root(lab, x);
+        y = uf_root(lab, y);
+        if (x == y) return;
+        if (x > y) {
+            const int32_t t = x;
+            x = y;
+            y = t;
+        }
+        const int32_t old = atomicMin(lab + y, x);
+        if (old == y) return;
+        y = old;
+    }
+}
+
+// Propagation pass: the smallest label among the cell's and its gas or
+// interface neighbours', then the label of the cell that label names.  Labels
+// only fall and only name cells of the same set.
+__global__ __launch_bounds__(BS) void k_bub_prop(StepArgs a, int32_t *lab) {
     const long long gid = (long long)blockIdx.x * BS + threadIdx.x;
-    if (gid >= a.g.BN || (k > 0 && flags[k - 1] == 0)) return;
+    if (gid >= a.g.BN) return;
     const int32_t l0 = lab[gid];
     if (l0 < 0) return;
     const Cell c = decode(a.g, gid);
@@ -83,22 +143,41 @@ __global__ __launch_bounds__(BS) void k_bub_pass(StepArgs a, int32_t *lab, int32
         const int32_t lq = q >= 0 ? lab[cb + q] : -1;
         m = (lq >= 0 && lq < m) ? lq : m;
     }
-    const int32_t mm = lab[m];   // the label of the cell m (a gas or interface cell)
+    const int32_t mm = lab[m];
     m = (mm >= 0 && mm < m) ? mm : m;
-    if (m < l0) {
-        lab[gid] = m;
-        flags[k] = 1;
-    }
+    if (m < l0) lab[gid] = m;
 }
 
-// Gas volume per label of lab1; with atm, the labels that reach the top layer;
-// with lab0, the gas volume of every start bubble's cells that are still gas
-// or interface.
-__global__ __launch_bounds__(BS) void k_bub_volume(StepArgs a, const int32_t *lab1, const double *phi,
-                                                   double *V, int32_t *atm, const int32_t *lab0,
-                                                   double *kept) {
+// Every link between two gas or interface cells, once (from the cell whose
+// direction index is the lower of the pair).
+__global__ __launch_bounds__(BS) void k_bub_merge(StepArgs a, int32_t *lab) {
     const long long gid = (long long)blockIdx.x * BS + threadIdx.x;
-    const int32_t l = gid < a.g.BN ? lab1[gid] : -1;
+    if (gid >= a.g.BN || lab[gid] < 0) return;
+    const Cell c = decode(a.g, gid);
+    const long long cb = (long long)c.b * a.g.N;
+    int32_t lq[Q];
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const int q = i < opp(i) ? nb_local(a.g, c.x, c.y, c.z, cx(i), cy(i), cz(i)) : -1;
+        lq[i] = q >= 0 ? lab[cb + q] : -1;
+    }
+#pragma unroll
+    for (int i = 1; i < Q; ++i)
+        if (i < opp(i) && lq[i] >= 0)
+            uf_join(lab, int32_t(gid), int32_t(cb + nb_local(a.g, c.x, c.y, c.z, cx(i), cy(i), cz(i))));
+}
+
+// Each cell's label (its root) into lab1, its gas volume added to its label's
+// V; with atm, the labels that reach the top layer; with lab0, the gas volume
+// of every start bubble's cells that are still gas or interface.
+__global__ __launch_bounds__(BS) void k_bub_volume(StepArgs a, int32_t *lab1, const double *phi, double *V,
+                                                   int32_t *atm, const int32_t *lab0, double *kept) {
+    const long long gid = (long long)blockIdx.x * BS + threadIdx.x;
+    int32_t l = gid < a.g.BN ? lab1[gid] : -1;
+    if (l >= 0) {
+        l = uf_root(lab1, int32_t(gid));
+        lab1[gid] = l;
+    }
     const double gv = l >= 0 ? gas_volume(phi[gid]) : 0.0;
     wave_add_by_label(l, gv, V);
     if (l >= 0 && atm && decode(a.g, gid).z == a.g.nz - 1) atm[l] = 1;
@@ -140,39 +219,16 @@ __global__ __launch_bounds__(BS) void k_bub_reset(StepArgs a, double *pbub) {
 
 unsigned blocks(const StepArgs &a) { return unsigned((a.g.BN + BS - 1) / BS); }
 
-// Label the gas and interface sets of the current flags into lab and clear
-// the sums z0..z3 (each BN entries, or null).  With tiles, also read back the
-// fluid-tile count in the same synchronisation and resize the bulk grid.
-bool label(fslbm_ctx *c, const StepArgs &a, int32_t *lab, double *z0, double *z1, double *z2, int32_t *z3,
-           bool tiles) {
-    int32_t *flags = at<int32_t>(c, c->L.bflag);
-    const int cap = int(bubble_pass_cap(c->p));
-    hipLaunchKernelGGL(k_bub_seed, dim3(blocks(a)), dim3(BS), 0, c->stream, a, lab, flags, cap, z0, z1, z2, z3);
-    if (!hip_ok(c, hipGetLastError(), "k_bub_seed")) return false;
-    std::vector<int32_t> h;
-    int done = 0, batch = std::max(2, c->bub_passes);
-    while (done < cap) {
-        const int n = std::min(batch, cap - done);
-        for (int j = 0; j < n; ++j)
-            hipLaunchKernelGGL(k_bub_pass, dim3(blocks(a)), dim3(BS), 0, c->stream, a, lab, flags, done + j);
-        h.assign(size_t(n) + 1, 0);
-        if (!hip_ok(c, hipGetLastError(), "k_bub_pass") ||
-            !hip_ok(c, hipMemcpyAsync(h.data(), flags + done, size_t(n) * 4, hipMemcpyDeviceToHost, c->stream),
-                    "hipMemcpy(bubble flags)") ||
-            (tiles && !hip_ok(c, hipMemcpyAsync(&h[n], at<int32_t>(c, c->L.cnt) + C_TILES, 4,
-                                                hipMemcpyDeviceToHost, c->stream), "hipMemcpy(tile count)")) ||
-            !hip_ok(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize"))
-            return false;
-        const int first_zero = int(std::find(h.begin(), h.begin() + n, 0) - h.begin());
-        if (first_zero < n) {
-            c->bub_passes = done + first_zero + 1;
-            return !tiles || resize_bulk_grid(c, h[n]);
-        }
-        done += n;
-        batch *= 2;
-    }
-    fail(c, FSLBM_EDEVICE, "bubble labels did not settle");
-    return false;
+// Label the gas and interface sets of the current flags into lab (roots and
+// volumes: k_bub_volume), clearing the sums V, amount, atm and, with lab0,
+// kept (each BN entries, or null).
+bool label(fslbm_ctx *c, hipStream_t st, const StepArgs &a, int32_t *lab, const int32_t *lab0, double *V,
+           double *kept, double *amount, int32_t *atm) {
+    hipLaunchKernelGGL(k_bub_seed, dim3(blocks(a)), dim3(BS), 0, st, a, lab, lab0, V, kept, amount, atm);
+    hipLaunchKernelGGL(k_bub_prop, dim3(blocks(a)), dim3(BS), 0, st, a, lab);
+    hipLaunchKernelGGL(k_bub_prop, dim3(blocks(a)), dim3(BS), 0, st, a, lab);
+    hipLaunchKernelGGL(k_bub_merge, dim3(blocks(a)), dim3(BS), 0, st, a, lab);
+    return hip_ok(c, hipGetLastError(), "bubble labels");
 }
 
 }  // namespace
@@ -188,14 +244,14 @@ bool bubble_begin(fslbm_ctx *c) {
     const StepArgs a = make_args(c, int(c->t & 1));
     int32_t *lab0 = at<int32_t>(c, c->L.blab0);
     double *V0 = at<double>(c, c->L.bV0);
-    if (!label(c, a, lab0, V0, nullptr, nullptr, nullptr, false)) return false;
+    if (!label(c, c->stream, a, lab0, nullptr, V0, nullptr, nullptr, nullptr)) return false;
     hipLaunchKernelGGL(k_bub_volume, dim3(blocks(a)), dim3(BS), 0, c->stream, a, lab0, a.phi_cur, V0,
                        static_cast<int32_t *>(nullptr), static_cast<const int32_t *>(nullptr),
                        static_cast<double *>(nullptr));
     return hip_ok(c, hipGetLastError(), "k_bub_volume");
 }
 
-bool bubble_end(fslbm_ctx *c) {
+bool bubble_end(fslbm_ctx *c, hipStream_t st) {
     // after the step: phi_cur of the next step's arguments is the step's result
     const StepArgs a = make_args(c, int(c->t & 1));
     int32_t *lab0 = at<int32_t>(c, c->L.blab0), *lab1 = at<int32_t>(c, c->L.blab1);
@@ -203,26 +259,18 @@ bool bubble_end(fslbm_ctx *c) {
     double *V0 = at<double>(c, c->L.bV0), *V1 = at<double>(c, c->L.bV1);
     double *kept = at<double>(c, c->L.bkept), *amount = at<double>(c, c->L.bamount);
     double *pbub = at<double>(c, c->L.pbub);
-    // the refills may have opened tiles: the bulk grid is resized from the
-    // tile count read with the labels
-    if (!label(c, a, lab1, V1, kept, amount, atm, true)) return false;
+    if (!label(c, st, a, lab1, lab0, V1, kept, amount, atm)) return false;
     const unsigned nb = blocks(a);
-    hipLaunchKernelGGL(k_bub_volume, dim3(nb), dim3(BS), 0, c->stream, a, lab1, a.phi_cur, V1, atm,
+    hipLaunchKernelGGL(k_bub_volume, dim3(nb), dim3(BS), 0, st, a, lab1, a.phi_cur, V1, atm,
                        static_cast<const int32_t *>(lab0), kept);
-    hipLaunchKernelGGL(k_bub_amount, dim3(nb), dim3(BS), 0, c->stream, a, lab0, lab1, a.phi_cur,
+    hipLaunchKernelGGL(k_bub_amount, dim3(nb), dim3(BS), 0, st, a, lab0, lab1, a.phi_cur,
                        static_cast<const double *>(pbub), static_cast<const double *>(V0),
                        static_cast<const double *>(kept), amount);
-    hipLaunchKernelGGL(k_bub_assign, dim3(nb), dim3(BS), 0, c->stream, a, lab1, static_cast<const double *>(V1),
+    hipLaunchKernelGGL(k_bub_assign, dim3(nb), dim3(BS), 0, st, a, lab1, static_cast<const double *>(V1),
                        static_cast<const double *>(amount), static_cast<const int32_t *>(atm), pbub);
     if (!hip_ok(c, hipGetLastError(), "bubble kernels")) return false;
     c->bub_ready = true;
     return true;
-}
-
-long long bubble_pass_cap(const fslbm_params &p) {
-    // each pass lowers at least one label while any is not final; pointer
-    // jumping makes the passes far fewer than a set's diameter
-    return 8LL * (p.nx + p.ny + p.nz) + 1024;
 }
 
 bool bubble_reset(fslbm_ctx *c) {

@@ -24,8 +24,8 @@ struct Layout {
     size_t cnt, nif, res, omega, grav, diag_d, diag_i;
     size_t tiles, tile_bits;
     // bubble model: per-cell pressure (the state), labels at the step's start
-    // and end, per-label sums, the label pass's change flag
-    size_t pbub, blab0, blab1, bV0, bV1, bkept, bamount, batm, bflag;
+    // and end, per-label sums
+    size_t pbub, blab0, blab1, bV0, bV1, bkept, bamount, batm;
     size_t total;
 };
 
@@ -53,7 +53,6 @@ struct fslbm_ctx {
     int bulk_grid = 1024;            // workgroups of the bulk kernel (tile-list stride)
     bool bub_ready = false;          // the bubble labels and volumes of the last step's end
                                      // are those of the next step's start
-    int bub_passes = 0;              // label passes of the last labelling, the unchanged one included
     fslbm::AdjointRun adj;
     int static_dev = -1;             // device whose static workspace backs this context
                                      // (fslbm_init_static), else -1
@@ -99,11 +98,9 @@ bool resize_bulk_grid(fslbm_ctx *c, int32_t fluid_tiles);
 bool enqueue_read(fslbm_ctx *c, uint32_t mask, void *const *dst);
 
 // Bubble model (bubble_model = 1): the bubbles and their volumes at the start
-// of a step, and their pressures at its end.  Both synchronise the stream.
-// The label passes' change flags take bubble_pass_cap(p) int32 entries.
-long long bubble_pass_cap(const fslbm_params &p);
+// of a step, and their pressures at its end (launches only, no waits).
 bool bubble_begin(fslbm_ctx *c);
-bool bubble_end(fslbm_ctx *c);
+bool bubble_end(fslbm_ctx *c, hipStream_t st);
 // Every gas and interface cell at p_volume (after a state is loaded).
 bool bubble_reset(fslbm_ctx *c);
 

@@ -65,18 +65,22 @@ def test_random_states_all_schemes(scheme):
         assert ref.counts is not None
 
 
-@pytest.mark.parametrize("collision,smag", [(0, 0.0), (1, 0.0), (1, 0.15)])
-def test_random_states_wide_rows(collision, smag):
+@pytest.mark.parametrize("collision,smag,periodic", [(0, 0.0, (1, 1, 0)), (1, 0.0, (1, 1, 0)),
+                                                     (1, 0.15, (1, 1, 0)), (1, 0.0, (0, 1, 0)),
+                                                     (0, 0.0, (0, 0, 0)), (1, 0.0, (1, 1, 1))])
+def test_random_states_wide_rows(collision, smag, periodic):
     """Rows of 192 cells: the tile in the middle of every interior row is
     updated through the bulk kernel's uniform-offset path in both step
-    parities, the tiles at the row ends and the boundary rows through the
-    general one.  One domain and a batch of two, one step per call and four."""
-    s0 = setups.random_interface_state(192, 12, 10, 40 + collision, periodic=(1, 1, 0),
+    parities, the tiles at the row ends and on the boundary rows through the
+    general one in the layout A -> B step, with walls or periodic wraps on
+    each pair of faces.  One domain and a batch of two, one step per call and
+    four."""
+    s0 = setups.random_interface_state(192, 12, 10, 40 + collision, periodic=periodic,
                                        g=(0.0, 0.0, -1e-4), collision=collision)
-    s1 = setups.random_interface_state(192, 12, 10, 50 + collision, periodic=(1, 1, 0),
+    s1 = setups.random_interface_state(192, 12, 10, 50 + collision, periodic=periodic,
                                        g=(0.0, 0.0, -1e-4), collision=collision)
     p = oracle_params(s0, smag_cs=smag)
-    announce(f"wide rows 192x12x10 collision {collision} smagorinsky {smag}")
+    announce(f"wide rows 192x12x10 collision {collision} smagorinsky {smag} periodic {periodic}")
     _run_pair(p, oracle_state(s0, p), 3, "wide rows")
     sts = [oracle_state(s0, p), oracle_state(s1, p)]
     sim = sim_from_states(p, sts)
