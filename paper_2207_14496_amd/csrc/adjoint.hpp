@@ -33,10 +33,12 @@ struct AdjArgs {
     // adjoints of the state at t (outputs)
     double *lf0, *lm0, *lphi0, *lres0;
     // per-step scratch
-    double *lfin;          // [B][19][N] adjoint of the streamed (pre-collision) PDFs at t+1
+    double *lua;           // [BN][3] anti-bounce-back velocity adjoint of interface cells next to gas
     double *lmt;           // [BN] adjoint of the mass after the exchange, m'
     double *lphis;         // [BN] adjoint of the fill level after streaming, phi'
     uint8_t *cls;          // [BN] forced filling/emptying class at t
+    int32_t *iflist;       // [BN] the interface cells at t (k_adj_classes)
+    int32_t *ifcnt;        // [3] list length by the parity of t + 1; [2] unused error slot
     double *sum_lm;        // [B] sum of interface-mass adjoints (reservoir spreading)
     double *gpart;         // [B][nblk][4] running (omega, gx, gy, gz) gradient partials
     // loss L_b = (1/T) sum_{t=1..T} (h_b(t) - h*_b(t))^2, h = sum of phi over x = x_probe

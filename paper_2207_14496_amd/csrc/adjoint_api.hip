@@ -30,7 +30,7 @@ struct AdjLayout {
     int nblk;             // workgroups per domain
     size_t rec_bytes;
     size_t h, dloss, ck, seg, fin;
-    size_t lf[2], lm[2], lphi[2], lres[2], lfin, lmt, lphis, cls, sum_lm, gpart, gred;
+    size_t lf[2], lm[2], lphi[2], lres[2], lua, lmt, lphis, cls, iflist, ifcnt, sum_lm, gpart, gred;
     size_t total;
 };
 
@@ -82,10 +82,12 @@ AdjLayout make_adj_layout(const fslbm_ctx *c, const fslbm_adjoint_spec &s) {
         L.lphi[k] = take(BN * 8);
         L.lres[k] = take(B * 8);
     }
-    L.lfin = take(BN * Q * 8);
+    L.lua = take(BN * 3 * 8);
     L.lmt = take(BN * 8);
     L.lphis = take(BN * 8);
     L.cls = take(BN);
+    L.iflist = take(BN * 4);
+    L.ifcnt = take(16);
     L.sum_lm = take(B * 8);
     L.gpart = take(B * size_t(L.nblk) * 4 * 8);
     L.gred = take(B * 4 * 8);
@@ -230,7 +232,8 @@ fslbm_status fslbm_adjoint_backward(fslbm_ctx *c, const fslbm_adjoint_spec *spec
          hip_ok(c, hipMemsetAsync(D(L.lm[0]), 0, BN * 8, c->stream), "hipMemset") &&
          hip_ok(c, hipMemsetAsync(D(L.lphi[0]), 0, BN * 8, c->stream), "hipMemset") &&
          hip_ok(c, hipMemsetAsync(D(L.lres[0]), 0, size_t(B) * 8, c->stream), "hipMemset") &&
-         hip_ok(c, hipMemsetAsync(D(L.gpart), 0, size_t(B) * L.nblk * 4 * 8, c->stream), "hipMemset");
+         hip_ok(c, hipMemsetAsync(D(L.gpart), 0, size_t(B) * L.nblk * 4 * 8, c->stream), "hipMemset") &&
+         hip_ok(c, hipMemsetAsync(ws + L.ifcnt, 0, 16, c->stream), "hipMemset");
     if (!ok) return c->status;
 
     StepArgs sa = make_args(c, 0);
@@ -241,10 +244,12 @@ fslbm_status fslbm_adjoint_backward(fslbm_ctx *c, const fslbm_adjoint_spec *spec
     a.omega = sa.omega;
     a.grav = sa.grav;
     a.rhoG = 3.0 * c->p.p_volume;
-    a.lfin = D(L.lfin);
+    a.lua = D(L.lua);
     a.lmt = D(L.lmt);
     a.lphis = D(L.lphis);
     a.cls = reinterpret_cast<uint8_t *>(ws + L.cls);
+    a.iflist = reinterpret_cast<int32_t *>(ws + L.iflist);
+    a.ifcnt = reinterpret_cast<int32_t *>(ws + L.ifcnt);
     a.sum_lm = D(L.sum_lm);
     a.gpart = D(L.gpart);
     a.h = D(L.h);

@@ -19,10 +19,13 @@
 //       phi = m / rho* on every cell whose mass changed (Sec. 2.2, excess-mass
 //       equation).
 // Its reverse runs S7/S6 (k_adj_receivers, k_adj_converted), S5
-// (k_adj_refill), S2 with phi' (k_adj_collide) and S1 as a gather over the
-// source cell (k_adj_stream).  Which cells converted, and which interface cells
+// (k_adj_refill), then S2 with phi' and S1 in one pass that pushes each
+// streamed population's adjoint back to its origin (k_adj_collide_stream, with
+// k_adj_abb_velocity for the anti-bounce-back's velocity term).  Which cells converted, and which interface cells
 // received excess mass, is read off the two canonical type fields; the
 // conversion decisions themselves are held fixed.
+#include <algorithm>
+
 #include "adjoint.hpp"
 
 namespace fslbm {
@@ -140,12 +143,24 @@ __device__ __forceinline__ void stream_in(const AdjArgs &a, const Cell &c, doubl
 // ------------------------------------------------------------------ kernels
 
 // Forced classes of the interface cells at t.
+// They are also listed (ifcnt by the parity of t + 1), for the kernels that
+// only act on interface cells; the other parity's count is cleared for the
+// next reverse step.
 __global__ __launch_bounds__(BS) void k_adj_classes(AdjArgs a) {
     const int b = blockIdx.y, n = blockIdx.x * BS + threadIdx.x;
     if (blockIdx.x == 0 && threadIdx.x == 0) a.sum_lm[b] = 0.0;
-    if (n >= a.g.N) return;
+    if (blockIdx.x == 0 && b == 0 && threadIdx.x == 0) a.ifcnt[1 - (a.t1 & 1)] = 0;
     const long long gid = (long long)b * a.g.N + n;
-    a.cls[gid] = a.s0.fl[gid] == F_IF ? uint8_t(type_class(a.g, a.s0.fl, cell_of(a.g, b, n))) : 0;
+    const bool itf = n < a.g.N && a.s0.fl[gid] == F_IF;
+    if (n < a.g.N) a.cls[gid] = itf ? uint8_t(type_class(a.g, a.s0.fl, cell_of(a.g, b, n))) : 0;
+    wave_append(itf, int32_t(gid), a.iflist, a.ifcnt + (a.t1 & 1), (long long)a.B * a.g.N, a.ifcnt + 2);
+}
+
+// Item k of the interface list as (domain, cell).
+__device__ __forceinline__ void if_item(const AdjArgs &a, long long k, int &b, int &n) {
+    const int32_t gid = a.iflist[k];
+    b = int(a.g.dN.div(uint32_t(gid)));
+    n = int(gid - (long long)b * a.g.N);
 }
 
 // S7 reverse on the cells that are interface at t+1.  The loss adds its
@@ -227,6 +242,17 @@ __global__ __launch_bounds__(BS) void k_adj_converted(AdjArgs a) {
         }
     } else if (ty0 == F_IF && ty1 == F_IF) {
         lmt = a.lm1[gid];
+        // phi(t+1) = phi' = m' / rho on an interface cell whose mass no
+        // excess touched (lphis, set by k_adj_receivers), with rho the
+        // streamed density
+        // (the collision keeps the density: rho = sum f*(t+1))
+        const double lp = a.lphis[gid];
+        if (lp != 0.0) {
+            double rho = 0.0;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) rho += a.s1.f[pidx(a.g, b, i, n)];
+            lmt += lp / rho;
+        }
     }
     a.lmt[gid] = lmt;
 }
@@ -317,9 +343,20 @@ __global__ __launch_bounds__(BS) void k_adj_refill(AdjArgs a) {
     block_add4(acc, a.gpart + ((long long)b * a.nblk + blockIdx.x) * 4);
 }
 
-// S2 reverse (SRT collision with Guo forcing) and phi' = m' / rho: adjoint of
-// the streamed populations at t+1 and the phi' part of the adjoint of m'.
-__global__ __launch_bounds__(BS) void k_adj_collide(AdjArgs a) {
+// S2 reverse (SRT collision with Guo forcing, and phi' = m' / rho) and S1
+// reverse in one pass over the cell x that the populations stream into.  The
+// collision's adjoint at x gives the adjoint lfin_i of every streamed
+// population f_i(x), which goes back to where that population came from: the
+// source cell y = x - c_i's entry i (f*_i(y)), with the mass-exchange terms of
+// the link between y and x, or x's own entry opp(i) at a wall (bounce-back) or
+// under anti-bounce-back from gas.  So every entry of the adjoint at t has one
+// writer: entry (j, y) is written by y + c_j when that cell is fluid, else by
+// y.  A cell's own terms are formed by its thread: the adjoints of m and phi
+// at t (gathered over its links) and the anti-bounce-back velocity term, which
+// touches all 19 of its entries and so is added afterwards (k_adj_abb_velocity,
+// from the sum this kernel leaves in lua).  The mass adjoints lmt read here
+// are final (k_adj_converted).
+__global__ __launch_bounds__(BS) void k_adj_collide_stream(AdjArgs a) {
     const int b = blockIdx.y, n = blockIdx.x * BS + threadIdx.x;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     const long long gid = (long long)b * a.g.N + n;
@@ -327,12 +364,56 @@ __global__ __launch_bounds__(BS) void k_adj_collide(AdjArgs a) {
         const uint8_t ty0 = a.s0.fl[gid];
         if (ty0 == F_GAS) {
 #pragma unroll
-            for (int i = 0; i < Q; ++i) a.lfin[pidx(a.g, b, i, n)] = 0.0;
+            for (int i = 0; i < Q; ++i) a.lf0[pidx(a.g, b, i, n)] = 0.0;
+            a.lm0[gid] = 0.0;
+            a.lphi0[gid] = 0.0;
         } else {
             const Cell c = cell_of(a.g, b, n);
-            double fin[Q];
-            stream_in(a, c, fin);
+            const long long cb = (long long)b * a.g.N;
             const double *gr = a.grav + 3 * b;
+            const bool xif = ty0 == F_IF;
+            // streamed populations (as stream_in): every source's flag and
+            // population in one round of loads (the cell's own slot at a wall);
+            // the cell's own f*(t) is only needed next to a wall or gas
+            double fin[Q];
+            uint8_t fls[Q];
+            int src[Q];
+            bool special = false;   // a wall or gas source
+            fin[0] = a.s0.f[pidx(a.g, b, 0, n)];
+#pragma unroll
+            for (int i = 1; i < Q; ++i) {
+                src[i] = nb_local(a.g, c.x, c.y, c.z, -cx(i), -cy(i), -cz(i));
+                const int sc = src[i] < 0 ? n : src[i];
+                fls[i] = src[i] < 0 ? uint8_t(0) : a.s0.fl[cb + sc];
+                fin[i] = a.s0.f[pidx(a.g, b, i, sc)];
+            }
+            issue_fence();
+#pragma unroll
+            for (int i = 1; i < Q; ++i) special |= fls[i] == 0 || fls[i] == F_GAS;
+            // u(x) from f*(t), the velocity of the anti-bounce-back
+            double ua[3] = {0.0, 0.0, 0.0};
+            if (special) {
+                double fs[Q];
+                double rs = 0.0, js[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    fs[i] = a.s0.f[pidx(a.g, b, i, n)];
+                    rs += fs[i];
+                    js[0] += cx(i) * fs[i]; js[1] += cy(i) * fs[i]; js[2] += cz(i) * fs[i];
+                }
+                for (int d = 0; d < 3; ++d) ua[d] = js[d] / rs - 0.5 * gr[d];
+                const double uu = ua[0] * ua[0] + ua[1] * ua[1] + ua[2] * ua[2];
+#pragma unroll
+                for (int i = 1; i < Q; ++i) {
+                    if (fls[i] == 0) {
+                        fin[i] = fs[opp(i)];
+                    } else if (fls[i] == F_GAS) {
+                        const double uc = cx(i) * ua[0] + cy(i) * ua[1] + cz(i) * ua[2];
+                        fin[i] = 2.0 * wgt<double>(i) * a.rhoG * (1.0 + 4.5 * uc * uc - 1.5 * uu) - fs[opp(i)];
+                    }
+                }
+            }
+            // S2 reverse: lfin = (d f*(t+1) / d fin)^T lf1(x)
             const double om = a.omega[b];
             double rho = 0.0, J[3] = {0.0, 0.0, 0.0};
 #pragma unroll
@@ -369,149 +450,178 @@ __global__ __launch_bounds__(BS) void k_adj_collide(AdjArgs a) {
                 }
             }
             for (int d = 0; d < 3; ++d) lrho += lF[d] * gr[d];   // F = rho g
-            // phi(t+1) = phi' = m' / rho on interface cells: its adjoint adds
-            // dr to every streamed population's adjoint
-            bool add_dr = false;
+            // phi(t+1) = phi' = m' / rho: its adjoint adds dr to every streamed
+            // population's (its m' part is in lmt already)
             double dr = 0.0;
-            if (ty0 == F_IF) {
+            if (xif) {
                 const double lp = a.lphis[gid];
-                if (lp != 0.0) {
-                    a.lmt[gid] += lp * irho;
-                    dr = -lp * a.s1.phi[gid] * irho;
-                    add_dr = true;
-                }
-            }
-            // (written out directly, not staged in registers: occupancy)
-#pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                const int ci[3] = {cx(i), cy(i), cz(i)};
-                double v = (1.0 - om) * lam[i] + lrho;
-                for (int d = 0; d < 3; ++d) v += lu[d] * (ci[d] - (u[d] - 0.5 * gr[d])) * irho;
-                if (add_dr) v += dr;
-                a.lfin[pidx(a.g, b, i, n)] = v;
+                if (lp != 0.0) dr = -lp * a.s1.phi[gid] * irho;
             }
             acc[0] = lom;
             for (int d = 0; d < 3; ++d) acc[1 + d] = lF[d] * rho + 0.5 * lu[d];
+            // S1 reverse, pushed back to each population's origin (the
+            // mass-exchange terms are added by k_adj_mass)
+            double lua[3] = {0.0, 0.0, 0.0};
+            // lam becomes the adjoint of the streamed populations, lfin
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const int ci[3] = {cx(i), cy(i), cz(i)};
+                double v = (1.0 - om) * lam[i] + lrho + dr;
+                for (int d = 0; d < 3; ++d) v += lu[d] * (ci[d] - (u[d] - 0.5 * gr[d])) * irho;
+                lam[i] = v;
+            }
+            // bounce-back (f_i(x) = f*_opp(i)(x)) and anti-bounce-back from gas
+            // (f_i(x) = feq_i + feq_opp(i) at (rho_G, u(x)) - f*_opp(i)(x)) go to
+            // the cell's own entry opp(i); a streamed f_i(x) = f*_i(y) to y's entry i
+            a.lf0[pidx(a.g, b, 0, n)] = lam[0];
+#pragma unroll
+            for (int i = 1; i < Q; ++i) {
+                const double li = lam[i];
+                const bool gas = src[i] >= 0 && fls[i] == F_GAS;
+                const bool own = src[i] < 0 || gas;
+                a.lf0[own ? pidx(a.g, b, opp(i), n) : pidx(a.g, b, i, src[i])] = gas ? -li : li;
+                const double lg = gas ? li : 0.0;
+                const double uc = cx(i) * ua[0] + cy(i) * ua[1] + cz(i) * ua[2];
+                const double k2 = 2.0 * wgt<double>(i) * a.rhoG;
+                lua[0] += lg * k2 * (9.0 * uc * cx(i) - 3.0 * ua[0]);
+                lua[1] += lg * k2 * (9.0 * uc * cy(i) - 3.0 * ua[1]);
+                lua[2] += lg * k2 * (9.0 * uc * cz(i) - 3.0 * ua[2]);
+            }
+            if (xif) {
+                // (zero without a gas neighbour)
+                for (int d = 0; d < 3; ++d) {
+                    a.lua[3 * gid + d] = lua[d];
+                    acc[1 + d] += -0.5 * lua[d];
+                }
+            } else {
+                a.lm0[gid] = 0.0;
+                a.lphi0[gid] = 0.0;
+            }
         }
     }
     block_add4(acc, a.gpart + ((long long)b * a.nblk + blockIdx.x) * 4);
 }
 
-// S1 reverse, gathered over the source cell y: every use of f*_i(y) --
-// streamed into y + c_i, bounced back at a wall, inside the anti-bounce-back of
-// y (directly and through u(y)), and in the mass-exchange links of y and of its
-// interface neighbours.  Also the adjoints of m(y, t) and phi(y, t).
-__global__ __launch_bounds__(BS) void k_adj_stream(AdjArgs a) {
-    const int b = blockIdx.y, n = blockIdx.x * BS + threadIdx.x;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+// The mass-exchange part of S1 reverse, run by the interface cells.  An entry
+// (i, y) of the adjoint at t that k_adj_collide_stream wrote from x = y + c_i
+// carries the link between y and x, whose terms depend on m' of whichever of
+// the two is interface.  Interface cell x adds them to the entries it wrote
+// (every fluid source y = x - c_i), and to its own entry (i, x) where x + c_i
+// is liquid (that entry's writer has no terms to add).  So each entry is
+// updated by one thread.  x also sets its own adjoints of m and phi at t.
+__device__ __forceinline__ void adj_mass_cell(const AdjArgs &a, const int b, const int n) {
     const long long gid = (long long)b * a.g.N + n;
-    if (n < a.g.N) {
-        const uint8_t ty0 = a.s0.fl[gid];
-        if (ty0 == F_GAS) {
+    const Cell c = cell_of(a.g, b, n);
+    const long long cb = (long long)b * a.g.N;
+    // the neighbours x + c_i (the source of direction opp(i) is x + c_i) and,
+    // in rounds of loads issued together, their types, then their fill
+    // levels, mass adjoints, classes and populations, then the entries to
+    // update (the cell itself stands in for a wall; unused there)
+    int qs[Q];
+    uint8_t tq[Q];
 #pragma unroll
-            for (int i = 0; i < Q; ++i) a.lf0[pidx(a.g, b, i, n)] = 0.0;
-            a.lm0[gid] = 0.0;
-            a.lphi0[gid] = 0.0;
-        } else {
-            const Cell c = cell_of(a.g, b, n);
-            const long long cb = (long long)b * a.g.N;
-            const double *gr = a.grav + 3 * b;
-            double fs[Q];
+    for (int i = 1; i < Q; ++i) {
+        qs[i] = nb_local(a.g, c.x, c.y, c.z, cx(i), cy(i), cz(i));
+        tq[i] = qs[i] < 0 ? uint8_t(0) : a.s0.fl[cb + qs[i]];
+    }
+    const double phx = a.s0.phi[gid];
+    const double lmtx = a.lmt[gid];
+    const int clx = a.cls[gid];
+    issue_fence();
+    double lphi = 0.0;
+    // two halves of nine directions, so that a half's loads fit the registers
 #pragma unroll
-            for (int i = 0; i < Q; ++i) fs[i] = a.s0.f[pidx(a.g, b, i, n)];
-            double rs = 0.0, js[3] = {0.0, 0.0, 0.0};
+    for (int h = 0; h < 2; ++h) {
+        constexpr int H = 9;
+        double phq[H], lmq[H], fq[H], fx[H], e_src[H], e_own[H];
+        int clq[H];
 #pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                rs += fs[i];
-                js[0] += cx(i) * fs[i]; js[1] += cy(i) * fs[i]; js[2] += cz(i) * fs[i];
+        for (int k = 0; k < H; ++k) {
+            const int i = 1 + h * H + k;
+            const int q = qs[i] < 0 ? n : qs[i];
+            const long long qg = cb + q;
+            phq[k] = a.s0.phi[qg];
+            lmq[k] = a.lmt[qg];
+            clq[k] = a.cls[qg];
+            fq[k] = a.s0.f[pidx(a.g, b, opp(i), q)];   // f*_opp(i)(x + c_i)
+            fx[k] = a.s0.f[pidx(a.g, b, i, n)];        // f*_i(x)
+            e_src[k] = a.lf0[pidx(a.g, b, opp(i), q)]; // entry (opp(i), x + c_i), streamed into x
+            e_own[k] = a.lf0[pidx(a.g, b, i, n)];      // entry (i, x), streamed into x + c_i
+        }
+        issue_fence();
+#pragma unroll
+        for (int k = 0; k < H; ++k) {
+            const int i = 1 + h * H + k;
+            if (qs[i] < 0) continue;
+            const int q = qs[i];
+            if (tq[i] == F_LIQ) {
+                // with a liquid neighbour q: f*_opp(i)(q) in, f*_i(x) out
+                a.lf0[pidx(a.g, b, opp(i), q)] = e_src[k] + lmtx;
+                a.lf0[pidx(a.g, b, i, n)] = e_own[k] - lmtx;
+            } else if (tq[i] == F_IF) {
+                // entry (opp(i), q): link opp(i) of q (out) and link i of x (in)
+                double ca, cbf, v;
+                flux_coef(clq[k], clx, ca, cbf);
+                v = lmq[k] * 0.5 * (phq[k] + phx) * cbf;
+                flux_coef(clx, clq[k], ca, cbf);
+                v += lmtx * 0.5 * (phx + phq[k]) * ca;
+                a.lf0[pidx(a.g, b, opp(i), q)] = e_src[k] + v;
+                // the fill-level adjoint of the link: link i of x (fin =
+                // f*_opp(i)(q), fout = f*_i(x)) and link opp(i) of q (fin =
+                // f*_i(x), fout = f*_opp(i)(q))
+                flux_coef(clx, clq[k], ca, cbf);
+                lphi += lmtx * 0.5 * (ca * fq[k] + cbf * fx[k]);
+                flux_coef(clq[k], clx, ca, cbf);
+                lphi += lmq[k] * 0.5 * (ca * fx[k] + cbf * fq[k]);
             }
-            const double ua[3] = {js[0] / rs - 0.5 * gr[0], js[1] / rs - 0.5 * gr[1], js[2] / rs - 0.5 * gr[2]};
-            const double phy = a.s0.phi[gid];
-            const bool yif = ty0 == F_IF;
-            const int cly = yif ? a.cls[gid] : 0;
-            const double lmty = a.lmt[gid];
-            double out[Q];
-            double lua[3] = {0.0, 0.0, 0.0};
-            double lphi = 0.0;
-            // every neighbour's flag, the streamed adjoint there and the
-            // cell's own adjoint of the opposite direction, in one round of
-            // loads (the cell itself stands in for a wall neighbour; unused)
-            int nbx[Q];
-            uint8_t txs[Q];
-            double lnb[Q], lop[Q];
-#pragma unroll
-            for (int i = 1; i < Q; ++i) {
-                nbx[i] = nb_local(a.g, c.x, c.y, c.z, cx(i), cy(i), cz(i));   // y + c_i
-                const int xc = nbx[i] < 0 ? n : nbx[i];
-                txs[i] = a.s0.fl[cb + xc];
-                lnb[i] = a.lfin[pidx(a.g, b, i, xc)];
-                lop[i] = a.lfin[pidx(a.g, b, opp(i), n)];
-            }
-            issue_fence();
-            out[0] = a.lfin[pidx(a.g, b, 0, n)];
-#pragma unroll
-            for (int i = 1; i < Q; ++i) {
-                const int xn = nbx[i];
-                const uint8_t tx = xn >= 0 ? txs[i] : 0;
-                double v = 0.0;
-                if (xn < 0) {
-                    v = lop[i];   // bounced back into y as opp(i)
-                } else if (tx == F_GAS) {
-                    // anti-bounce-back into y along opp(i) subtracts f*_i(y) and uses u(y)
-                    const int o = opp(i);
-                    const double l = lop[i];
-                    v = -l;
-                    const int co[3] = {cx(o), cy(o), cz(o)};
-                    const double uc = co[0] * ua[0] + co[1] * ua[1] + co[2] * ua[2];
-                    const double k2 = 2.0 * wgt<double>(o) * a.rhoG;
-                    for (int d = 0; d < 3; ++d) lua[d] += l * k2 * (9.0 * uc * co[d] - 3.0 * ua[d]);
-                } else {
-                    v = lnb[i];   // streamed into y + c_i
-                    const double fin_y = a.s0.f[pidx(a.g, b, opp(i), xn)];   // f*_opp(i)(y + c_i)
-                    const double fout_y = fs[i];                             // f*_i(y)
-                    const double phx = a.s0.phi[cb + xn];
-                    if (yif) {
-                        // link i of y carries fout = f*_i(y)
-                        if (tx == F_LIQ) {
-                            v -= lmty;
-                        } else {
-                            double ca, cbf;
-                            flux_coef(cly, a.cls[cb + xn], ca, cbf);
-                            v += lmty * 0.5 * (phy + phx) * cbf;
-                            lphi += lmty * 0.5 * (ca * fin_y + cbf * fout_y);
-                        }
-                    }
-                    if (tx == F_IF) {
-                        // link opp(i) of x = y + c_i carries fin = f*_i(y), fout = fin_y
-                        const double lmtx = a.lmt[cb + xn];
-                        if (!yif) {
-                            v += lmtx;
-                        } else {
-                            double ca, cbf;
-                            flux_coef(a.cls[cb + xn], cly, ca, cbf);
-                            v += lmtx * 0.5 * (phx + phy) * ca;
-                            lphi += lmtx * 0.5 * (ca * fout_y + cbf * fin_y);
-                        }
-                    }
-                }
-                out[i] = v;
-            }
-            if (lua[0] != 0.0 || lua[1] != 0.0 || lua[2] != 0.0) {
-                // u(y) = sum c f*(y) / rho*(y) - g/2
-#pragma unroll
-                for (int j = 0; j < Q; ++j) {
-                    const int cj[3] = {cx(j), cy(j), cz(j)};
-                    for (int d = 0; d < 3; ++d) out[j] += lua[d] * (cj[d] - (ua[d] + 0.5 * gr[d])) / rs;
-                }
-                for (int d = 0; d < 3; ++d) acc[1 + d] = -0.5 * lua[d];
-            }
-#pragma unroll
-            for (int i = 0; i < Q; ++i) a.lf0[pidx(a.g, b, i, n)] = out[i];
-            a.lm0[gid] = yif ? lmty : 0.0;
-            a.lphi0[gid] = yif ? lphi : 0.0;
         }
     }
-    block_add4(acc, a.gpart + ((long long)b * a.nblk + blockIdx.x) * 4);
+    a.lm0[gid] = lmtx;
+    a.lphi0[gid] = lphi;
+}
+
+__global__ __launch_bounds__(BS) void k_adj_mass(AdjArgs a) {
+    const long long cnt = a.ifcnt[a.t1 & 1];
+    for (long long k = (long long)blockIdx.x * BS + threadIdx.x; k < cnt; k += (long long)gridDim.x * BS) {
+        int b, n;
+        if_item(a, k, b, n);
+        adj_mass_cell(a, b, n);
+    }
+}
+
+// The anti-bounce-back velocity term of the interface cells next to gas: u(x)
+// = sum c f*(x) / rho*(x) - g/2 enters every one of x's 19 entries.  lua is
+// zero on interface cells without a gas neighbour.
+__device__ __forceinline__ void adj_abb_cell(const AdjArgs &a, const int b, const int n) {
+    const long long gid = (long long)b * a.g.N + n;
+    const double lua[3] = {a.lua[3 * gid], a.lua[3 * gid + 1], a.lua[3 * gid + 2]};
+    if (lua[0] == 0.0 && lua[1] == 0.0 && lua[2] == 0.0) return;
+    const double *gr = a.grav + 3 * b;
+    double fs[Q];
+    double rs = 0.0, js[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        fs[i] = a.s0.f[pidx(a.g, b, i, n)];
+        rs += fs[i];
+        js[0] += cx(i) * fs[i]; js[1] += cy(i) * fs[i]; js[2] += cz(i) * fs[i];
+    }
+    const double ua[3] = {js[0] / rs - 0.5 * gr[0], js[1] / rs - 0.5 * gr[1], js[2] / rs - 0.5 * gr[2]};
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+        const int cj[3] = {cx(j), cy(j), cz(j)};
+        double v = 0.0;
+        for (int d = 0; d < 3; ++d) v += lua[d] * (cj[d] - (ua[d] + 0.5 * gr[d])) / rs;
+        a.lf0[pidx(a.g, b, j, n)] += v;
+    }
+}
+
+__global__ __launch_bounds__(BS) void k_adj_abb_velocity(AdjArgs a) {
+    const long long cnt = a.ifcnt[a.t1 & 1];
+    for (long long k = (long long)blockIdx.x * BS + threadIdx.x; k < cnt; k += (long long)gridDim.x * BS) {
+        int b, n;
+        if_item(a, k, b, n);
+        adj_abb_cell(a, b, n);
+    }
 }
 
 // Interface height: h = sum of phi over the plane x = x_probe, one workgroup
@@ -572,8 +682,13 @@ void launch_adjoint_step(const AdjArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(k_adj_receivers, grid, dim3(BS), 0, s, a);
     hipLaunchKernelGGL(k_adj_converted, grid, dim3(BS), 0, s, a);
     hipLaunchKernelGGL(k_adj_refill, grid, dim3(BS), 0, s, a);
-    hipLaunchKernelGGL(k_adj_collide, grid, dim3(BS), 0, s, a);
-    hipLaunchKernelGGL(k_adj_stream, grid, dim3(BS), 0, s, a);
+    hipLaunchKernelGGL(k_adj_collide_stream, grid, dim3(BS), 0, s, a);
+    // the interface-cell kernels stride over the list (a fixed grid: its
+    // length is only known on the device)
+    const long long cells = (long long)a.B * a.g.N;
+    const unsigned nl = unsigned(std::min<long long>((cells + BS - 1) / BS, 1024));
+    hipLaunchKernelGGL(k_adj_mass, dim3(nl), dim3(BS), 0, s, a);
+    hipLaunchKernelGGL(k_adj_abb_velocity, dim3(nl), dim3(BS), 0, s, a);
 }
 
 void launch_height(const Geom &g, int B, const double *phi, int x_probe, double *h, long long stride,
