@@ -146,6 +146,18 @@ typedef struct fslbm_params {
                              * Steps run without graphs and without the fused
                              * excess work; fslbm_step_timed and the reverse mode
                              * reject it.                                          */
+    int32_t diag_every;     /* stability check period K (Sec. 4: the solver is
+                             * stable while |u| stays below c_s = 1/sqrt(3)):
+                             * 0 off; K > 0: fslbm_step runs the diagnostics
+                             * of fslbm_diagnostics after every step whose
+                             * count since the state was loaded is a multiple
+                             * of K (each check synchronises the stream) and
+                             * returns FSLBM_EUNSTABLE at the first check that
+                             * finds a non-finite value or a speed above c_s in
+                             * some domain, without running the remaining steps
+                             * and without poisoning the context
+                             * (fslbm_last_error says where).  The checks do not
+                             * change the steps' arithmetic.                    */
 } fslbm_params;
 
 typedef struct fslbm_ctx fslbm_ctx;

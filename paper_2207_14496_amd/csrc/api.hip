@@ -90,6 +90,7 @@ const char *validate(const fslbm_params *p) {
     if (!(p->smagorinsky_cs >= 0.0) || !(p->smagorinsky_cs < 1e3)) return "smagorinsky_cs must be finite and >= 0";
     if (p->free_slip != 0 && p->free_slip != 1) return "free_slip must be 0 or 1";
     if (p->bubble_model != 0 && p->bubble_model != 1) return "bubble_model must be 0 or 1";
+    if (p->diag_every < 0) return "diag_every must be >= 0";
     if (p->omega_b)
         for (int b = 0; b < p->batch; ++b)
             if (!(p->omega_b[b] > 0.0 && p->omega_b[b] < 2.0)) return "omega_b must lie in (0, 2)";
@@ -571,6 +572,26 @@ bool resize_bulk_grid(fslbm_ctx *c, int32_t n) {
     return true;
 }
 
+// The stability check of fslbm_params.diag_every after a step: the
+// diagnostics, when the step count since the load is a multiple of the period.
+fslbm_status check_stability(fslbm_ctx *c) {
+    const int K = c->p.diag_every;
+    if (K <= 0 || c->t % K != 0) return FSLBM_OK;
+    std::vector<fslbm_diag> d(size_t(c->p.batch));
+    const fslbm_status st = run_diagnostics(c, d.data());
+    if (st == FSLBM_EUNSTABLE && c->status == FSLBM_OK) {
+        const double cs = 1.0 / std::sqrt(3.0);
+        for (int b = 0; b < c->p.batch; ++b)
+            if (!d[b].finite || !(d[b].max_speed <= cs)) {
+                c->err = "stability check after step " + std::to_string(c->t) + ": domain " + std::to_string(b) +
+                         (d[b].finite ? " has |u| = " + std::to_string(d[b].max_speed) + " > c_s"
+                                      : " holds non-finite values");
+                break;
+            }
+    }
+    return st;
+}
+
 bool enqueue_read(fslbm_ctx *c, uint32_t mask, void *const *dst) {
     if (!mask) return true;
     ReadArgs r{};
@@ -722,13 +743,23 @@ fslbm_status fslbm_step(fslbm_ctx *c, int32_t nsteps) {
             c->pending = false;
             ++c->t;
             if (!bubble_end(c, c->stream)) return c->status;
+            const fslbm_status st = check_stability(c);
+            if (st != FSLBM_OK) return st;
         }
         return FSLBM_OK;
     }
     // each step's excess-mass redistribution runs inside the next step's bulk
-    // kernel; the last step finishes its own
-    for (int32_t s = 0; s < nsteps; ++s)
-        if (!enqueue_step(c, s + 1 == nsteps)) return c->status;
+    // kernel; the last step finishes its own, and so does a step that a
+    // stability check follows
+    const int K = c->p.diag_every;
+    for (int32_t s = 0; s < nsteps; ++s) {
+        const bool checked = K > 0 && (c->t + 1) % K == 0;
+        if (!enqueue_step(c, s + 1 == nsteps || checked)) return c->status;
+        if (checked) {
+            const fslbm_status st = check_stability(c);
+            if (st != FSLBM_OK) return st;
+        }
+    }
     return FSLBM_OK;
 }
 
@@ -823,10 +854,14 @@ fslbm_status fslbm_read_fields(fslbm_ctx *c, uint32_t mask, void *const *dst) {
     return FSLBM_OK;
 }
 
-fslbm_status fslbm_diagnostics(fslbm_ctx *c, fslbm_diag *out) {
-    if (!c) return FSLBM_EINVAL;
-    if (c->status != FSLBM_OK) return c->status;
-    if (!out) return fail(c, FSLBM_EINVAL, "out is NULL");
+}  // extern "C"
+
+namespace fslbm {
+
+// Per-domain diagnostics into out[B] (synchronises): FSLBM_EUNSTABLE if some
+// domain holds non-finite values or a speed above c_s, else OK (or the
+// context's failure).
+fslbm_status run_diagnostics(fslbm_ctx *c, fslbm_diag *out) {
     const int B = c->p.batch;
     StepArgs a = make_args(c, int(c->t & 1));
     double *pd = at<double>(c, c->L.diag_d);
@@ -872,6 +907,17 @@ fslbm_status fslbm_diagnostics(fslbm_ctx *c, fslbm_diag *out) {
         out[b] = d;
     }
     return unstable ? FSLBM_EUNSTABLE : FSLBM_OK;
+}
+
+}  // namespace fslbm
+
+extern "C" {
+
+fslbm_status fslbm_diagnostics(fslbm_ctx *c, fslbm_diag *out) {
+    if (!c) return FSLBM_EINVAL;
+    if (c->status != FSLBM_OK) return c->status;
+    if (!out) return fail(c, FSLBM_EINVAL, "out is NULL");
+    return run_diagnostics(c, out);
 }
 
 fslbm_status fslbm_last_step_stats(fslbm_ctx *c, fslbm_step_stats *out) {

@@ -94,6 +94,10 @@ bool refresh_bulk_grid(fslbm_ctx *c);
 // The same from a fluid-tile count the caller has read back.
 bool resize_bulk_grid(fslbm_ctx *c, int32_t fluid_tiles);
 
+// Per-domain diagnostics into out[B] (synchronises); FSLBM_EUNSTABLE if some
+// domain holds non-finite values or a speed above c_s.
+fslbm_status run_diagnostics(fslbm_ctx *c, fslbm_diag *out);
+
 // Enqueue the canonical read-back of the fields in `mask` (no synchronisation).
 bool enqueue_read(fslbm_ctx *c, uint32_t mask, void *const *dst);
 

@@ -52,7 +52,7 @@ class CParams(ctypes.Structure):
                 ("eps_phi", ctypes.c_double), ("omega_b", ctypes.POINTER(ctypes.c_double)),
                 ("gravity_b", ctypes.POINTER(ctypes.c_double)), ("stream", ctypes.c_void_p),
                 ("smagorinsky_cs", ctypes.c_double), ("free_slip", ctypes.c_int32),
-                ("bubble_model", ctypes.c_int32)]
+                ("bubble_model", ctypes.c_int32), ("diag_every", ctypes.c_int32)]
 
 
 class CDiag(ctypes.Structure):
@@ -137,6 +137,7 @@ class Params:
     smagorinsky_cs: float = 0.0       # Smagorinsky constant (0 = no turbulence model)
     free_slip: int = 0                # walls: 0 no-slip, 1 free-slip (specular)
     bubble_model: int = 0             # 1: per-bubble volume pressures
+    diag_every: int = 0               # stability check period in steps (0 = off)
 
     @property
     def N(self) -> int:
@@ -154,6 +155,7 @@ class Params:
         p.smagorinsky_cs = float(self.smagorinsky_cs)
         p.free_slip = int(self.free_slip)
         p.bubble_model = int(self.bubble_model)
+        p.diag_every = int(self.diag_every)
         keep = []
         if self.omega_b is not None:
             arr = (ctypes.c_double * self.batch)(*[float(v) for v in self.omega_b])
