@@ -26,6 +26,9 @@ standing_wave_cpu  the 64 x 128 standing wave (SRT omega = 1.8, g = 1e-5, EQ,
 variants   other storage types, the dense pool-wave case (83% fluid), and the
            reduced-precision error against the FP64 run.
 wave_frequency  the Sec. 4.1 gravity wave at L = 400 in every storage type.
+storage_speedup  per workload, FP32, FP16 and BF16 storage against FP64 and
+           FP32 (whole step and bulk kernel), each beside its error against the
+           FP64 run (fill level, interface height, wave half-periods).
 gravity_wave_schemes  (--gravity-wave-schemes) the same wave at L = 800 (FP64)
            with each refilling scheme, next to the per-scheme series the paper prints.
 dam_break  rectangular dam break 256 x 128 x 64 (FP32), each refilling scheme,
@@ -274,6 +277,7 @@ def main():
     if not args.no_variants:
         result["variants"] = variants(fslbm, setups, torch, args)
         result["wave_frequency"] = wave_frequency(fslbm)
+        result["storage_speedup"] = storage_speedup(result["variants"], result["wave_frequency"])
     if args.gravity_wave_schemes:
         result["gravity_wave_schemes"] = gravity_wave_schemes(fslbm)
     if not args.no_reports:
@@ -287,6 +291,33 @@ def main():
         result["cpu_baseline"] = cpu_baseline(setup)
         result["standing_wave_cpu"] = standing_wave_cpu(fslbm, setups, torch)
     print(json.dumps(result), flush=True)
+
+
+def storage_speedup(variants, wave):
+    """Each reduced-precision storage type against FP32 and FP64 storage on the
+    same workload (per step and per bulk launch), beside its measured error
+    against the FP64 run: the 300-step variants' fill-level and interface-height
+    differences, and the gravity wave's half-period error."""
+    wave_err = {w["storage"]: w.get("rel_err_vs_f64") for w in wave}
+    out = {}
+    for wl in sorted({v["workload"] for v in variants}):
+        rows = {v["storage"]: v for v in variants if v["workload"] == wl}
+        if "f32" not in rows or "f64" not in rows:
+            continue
+        rec = {}
+        for name in ("f32", "f16", "bf16"):
+            if name not in rows:
+                continue
+            v = rows[name]
+            rec[name] = {
+                "step_over_f64": round(rows["f64"]["ms_per_step"] / v["ms_per_step"], 3),
+                "step_over_f32": round(rows["f32"]["ms_per_step"] / v["ms_per_step"], 3),
+                "bulk_over_f64": round(rows["f64"]["bulk_kernel_ms"] / v["bulk_kernel_ms"], 3),
+                "bulk_over_f32": round(rows["f32"]["bulk_kernel_ms"] / v["bulk_kernel_ms"], 3),
+                "error_vs_f64": dict(v.get("vs_f64", {}), wave_half_period_rel=wave_err.get(name)),
+            }
+        out[wl] = rec
+    return out
 
 
 def wave_frequency(fslbm, L=400, t_star_end=10.0):
