@@ -219,12 +219,11 @@ __global__ void k_init_lists(StepArgs a) {
 }
 
 // The tiles (one wavefront of consecutive cells each) that hold liquid or
-// interface cells.
-// The list and its bits start empty; one list atomic per workgroup.
+// interface cells: first their membership bits (one atomic per workgroup),
+// then the list itself in tile order (k_tile_list).
 __global__ __launch_bounds__(256) void k_init_tiles(StepArgs a) {
     static_assert(TILE == 64, "one tile per wavefront");
     __shared__ uint32_t has;
-    __shared__ int32_t base;
     const long long gid = (long long)blockIdx.x * 256 + threadIdx.x;
     const bool fluid = gid < a.g.BN && (a.flags[gid] & (F_LIQ | F_IF));
     const int w = int(threadIdx.x >> 6);
@@ -234,15 +233,45 @@ __global__ __launch_bounds__(256) void k_init_tiles(StepArgs a) {
     if (any && __lane_id() == 0) atomicOr(&has, 1u << w);
     __syncthreads();
     const int32_t t0 = int32_t(blockIdx.x) * 4;   // the workgroup's four tiles share one bit word
-    if (threadIdx.x == 0 && has) {
-        base = atomicAdd(a.cnt + C_TILES, __popc(has));
-        atomicOr(a.tile_bits + (t0 >> 5), has << (t0 & 31));
+    if (threadIdx.x == 0 && has) atomicOr(a.tile_bits + (t0 >> 5), has << (t0 & 31));
+}
+
+// The tile list from the membership bits, in ascending tile order, and its
+// length.  One workgroup of 1024 threads; thread t takes a contiguous run of
+// bit words, so the list order is the memory order of the cells.  The bulk
+// kernel's wavefronts take consecutive list entries, so neighbouring tiles
+// are updated side by side (on the dense pool, 701 -> 642 us per FP32 bulk
+// launch against the order of the workgroups' atomics).  Runs once per load.
+__global__ __launch_bounds__(1024) void k_tile_list(StepArgs a) {
+    __shared__ int32_t wave_sum[16];
+    const long long nwords = (tile_count(a.g.BN) + 31) / 32;
+    const long long per = (nwords + blockDim.x - 1) / blockDim.x;
+    const long long s0 = (long long)threadIdx.x * per;
+    const long long w0 = s0 < nwords ? s0 : nwords;
+    const long long w1 = w0 + per < nwords ? w0 + per : nwords;
+    int32_t n = 0;
+    for (long long w = w0; w < w1; ++w) n += __popc(a.tile_bits[w]);
+    // exclusive prefix of n over the workgroup: in each wavefront by
+    // shuffles, then over the sixteen wavefronts through shared memory
+    const int lane = __lane_id(), wv = int(threadIdx.x >> 6);
+    int32_t x = n;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
     }
+    if (lane == 63) wave_sum[wv] = x;
     __syncthreads();
-    if (any && __lane_id() == 0) {
-        const int32_t pos = base + __popc(has & ((1u << w) - 1u));
-        if (pos < int32_t(tile_count(a.g.BN))) a.tiles[pos] = t0 + w;
+    int32_t pos = x - n;
+    for (int k = 0; k < wv; ++k) pos += wave_sum[k];
+    for (long long w = w0; w < w1; ++w) {
+        uint32_t bits = a.tile_bits[w];
+        while (bits) {
+            a.tiles[pos++] = int32_t(w * 32 + (__ffs(bits) - 1));
+            bits &= bits - 1u;
+        }
     }
+    if (threadIdx.x == blockDim.x - 1) a.cnt[C_TILES] = pos;
 }
 
 // ------------------------------------------------------------------ read-back
@@ -549,6 +578,8 @@ bool load_state(fslbm_ctx *c, const uint8_t *flags, const double *phi, const dou
     if (!hip_ok(c, hipGetLastError(), "k_init_lists")) return false;
     hipLaunchKernelGGL(k_init_tiles, dim3(nblk), dim3(256), 0, c->stream, a);
     if (!hip_ok(c, hipGetLastError(), "k_init_tiles")) return false;
+    hipLaunchKernelGGL(k_tile_list, dim3(1), dim3(1024), 0, c->stream, a);
+    if (!hip_ok(c, hipGetLastError(), "k_tile_list")) return false;
     return !c->p.bubble_model || bubble_reset(c);
 }
 

@@ -348,10 +348,12 @@ __device__ __forceinline__ void slist_reset(const SList &L) {
 }
 
 // Append the entries val(i) of every lane whose bit i is set in sel (i < NI),
-// one reservation per wavefront on the wavefront's slot.  Must be called by
-// all lanes of the wavefront that are active in the enclosing loop.
+// one reservation per wavefront.  The slot is the wavefront's global index
+// modulo S, or key modulo S for a key >= 0 (the same on all lanes), which sets
+// where in the list's order the entries land.  Must be called by all lanes of
+// the wavefront that are active in the enclosing loop.
 template <int NI, typename V>
-__device__ __forceinline__ void slist_append_sel(const SList &L, uint32_t sel, V val, int32_t *err) {
+__device__ __forceinline__ void slist_append_sel(const SList &L, uint32_t sel, V val, int32_t *err, int key = -1) {
     unsigned long long masks[NI];
     int pre[NI];
     int tot = 0;
@@ -365,7 +367,8 @@ __device__ __forceinline__ void slist_append_sel(const SList &L, uint32_t sel, V
     const unsigned long long active = __ballot(1);
     const int lane = __lane_id();
     const int leader = __ffsll((long long)active) - 1;
-    const int slot = int(((blockIdx.x * blockDim.x + threadIdx.x) >> 6) % unsigned(L.S));
+    const int slot = key >= 0 ? int(unsigned(key) % unsigned(L.S))
+                              : int(((blockIdx.x * blockDim.x + threadIdx.x) >> 6) % unsigned(L.S));
     int base = 0, obase = 0;
     if (lane == leader) {
         base = atomicAdd(L.cnt + 32 * slot, tot);
@@ -391,8 +394,8 @@ __device__ __forceinline__ void slist_append_sel(const SList &L, uint32_t sel, V
     }
 }
 
-__device__ __forceinline__ void slist_append(const SList &L, bool pred, int32_t v, int32_t *err) {
-    slist_append_sel<1>(L, pred ? 1u : 0u, [&](int) { return v; }, err);
+__device__ __forceinline__ void slist_append(const SList &L, bool pred, int32_t v, int32_t *err, int key = -1) {
+    slist_append_sel<1>(L, pred ? 1u : 0u, [&](int) { return v; }, err, key);
 }
 
 // Read side: prefix sums of the clamped slot lengths in shared memory (every
