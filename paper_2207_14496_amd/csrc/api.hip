@@ -486,7 +486,7 @@ bool device_errors_ok(fslbm_ctx *c) {
 }
 
 void drop_graphs(fslbm_ctx *c) {
-    for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < 8; ++k)
         if (c->exec[k]) { (void)hipGraphExecDestroy(c->exec[k]); c->exec[k] = nullptr; }
 }
 
@@ -507,6 +507,28 @@ bool capture(fslbm_ctx *c, int parity, int pending) {
     hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
     if (!hip_ok(c, le, "kernel launch (capture)") || !hip_ok(c, e, "hipStreamEndCapture")) return false;
     hipError_t ie = hipGraphInstantiate(&c->exec[parity + 2 * pending], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    return hip_ok(c, ie, "hipGraphInstantiate");
+}
+
+// A step with the bubble model whose start labels are the last step's end
+// labels (bubble_begin has swapped them in): the step with its own excess
+// work, then the labels and pressures of its end, as graph v.
+bool capture_bubble_step(fslbm_ctx *c, int parity, int v) {
+    if (!c->cap_stream &&
+        !hip_ok(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "hipStreamCreate"))
+        return false;
+    hipGraph_t g = nullptr;
+    if (!hip_ok(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal),
+                "hipStreamBeginCapture"))
+        return false;
+    launch_step(make_args(c, parity), c->p.storage, c->p.collision, c->p.refill, c->cap_stream, nullptr,
+                nullptr, true);
+    const bool ok = bubble_end(c, c->cap_stream, 1 - parity);
+    hipError_t le = hipGetLastError();
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    if (!ok || !hip_ok(c, le, "kernel launch (capture)") || !hip_ok(c, e, "hipStreamEndCapture")) return false;
+    hipError_t ie = hipGraphInstantiate(&c->exec[v], g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     return hip_ok(c, ie, "hipGraphInstantiate");
 }
@@ -764,16 +786,26 @@ fslbm_status fslbm_step(fslbm_ctx *c, int32_t nsteps) {
     if (c->status != FSLBM_OK) return c->status;
     if (nsteps < 0) return fail(c, FSLBM_EINVAL, "nsteps must be >= 0");
     if (c->p.bubble_model) {
-        // the bubbles of the step's start, the step with direct launches and
-        // its own excess work, then the bubble pressures of its end
+        // the bubbles of the step's start, the step with its own excess work,
+        // then the bubble pressures of its end (one graph once the start labels
+        // are the last step's end labels)
         for (int32_t s = 0; s < nsteps; ++s) {
+            const bool replay = c->graphs && c->bub_ready;
             if (!bubble_begin(c)) return c->status;
-            launch_step(make_args(c, int(c->t & 1)), c->p.storage, c->p.collision, c->p.refill, c->stream,
-                        nullptr, nullptr, true);
-            if (!hip_ok(c, hipGetLastError(), "step kernel launch")) return c->status;
+            const int parity = int(c->t & 1);
+            if (replay) {
+                const int v = 4 + parity + 2 * (c->L.blab0 < c->L.blab1 ? 0 : 1);
+                if (!c->exec[v] && !capture_bubble_step(c, parity, v)) return c->status;
+                if (!hip_ok(c, hipGraphLaunch(c->exec[v], c->stream), "hipGraphLaunch")) return c->status;
+                c->bub_ready = true;
+            } else {
+                launch_step(make_args(c, parity), c->p.storage, c->p.collision, c->p.refill, c->stream,
+                            nullptr, nullptr, true);
+                if (!hip_ok(c, hipGetLastError(), "step kernel launch")) return c->status;
+                if (!bubble_end(c, c->stream, 1 - parity)) return c->status;
+            }
             c->pending = false;
             ++c->t;
-            if (!bubble_end(c, c->stream)) return c->status;
             const fslbm_status st = check_stability(c);
             if (st != FSLBM_OK) return st;
         }

@@ -21,9 +21,10 @@
 // Hawick, IEEE TPDS 2018, with path halving); a last pass takes each cell's
 // root, the smallest index of its tree, and adds its gas volume to it.  A
 // fixed number of launches, whatever the sets' shapes, and no host
-// synchronisation.  Per-label sums are double atomics.  The model runs with
-// direct launches between the steps (fslbm_step), for the runs with enclosed
-// gas.
+// synchronisation.  Per-label sums are double atomics.  The model runs
+// between the steps (fslbm_step), for the runs with enclosed gas; a step whose
+// start labels are the last step's end labels replays the step and these
+// launches as one HIP graph.
 #include <algorithm>
 #include <utility>
 #include <vector>
@@ -251,9 +252,10 @@ bool bubble_begin(fslbm_ctx *c) {
     return hip_ok(c, hipGetLastError(), "k_bub_volume");
 }
 
-bool bubble_end(fslbm_ctx *c, hipStream_t st) {
-    // after the step: phi_cur of the next step's arguments is the step's result
-    const StepArgs a = make_args(c, int(c->t & 1));
+bool bubble_end(fslbm_ctx *c, hipStream_t st, int parity) {
+    // after the step: phi_cur of the next step's arguments (parity: the next
+    // step's) is the step's result
+    const StepArgs a = make_args(c, parity);
     int32_t *lab0 = at<int32_t>(c, c->L.blab0), *lab1 = at<int32_t>(c, c->L.blab1);
     int32_t *atm = at<int32_t>(c, c->L.batm);
     double *V0 = at<double>(c, c->L.bV0), *V1 = at<double>(c, c->L.bV1);

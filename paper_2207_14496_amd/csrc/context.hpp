@@ -48,7 +48,8 @@ struct fslbm_ctx {
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
     bool graphs = true;
-    hipGraphExec_t exec[4] = {nullptr, nullptr, nullptr, nullptr};   // [parity + 2 * pending]
+    // [parity + 2 * pending]; with the bubble model [4 + parity + 2 * (label buffers swapped)]
+    hipGraphExec_t exec[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     bool pending = false;            // the last step's excess-mass redistribution has not run yet
     int bulk_grid = 1024;            // workgroups of the bulk kernel (tile-list stride)
     bool bub_ready = false;          // the bubble labels and volumes of the last step's end
@@ -104,7 +105,7 @@ bool enqueue_read(fslbm_ctx *c, uint32_t mask, void *const *dst);
 // Bubble model (bubble_model = 1): the bubbles and their volumes at the start
 // of a step, and their pressures at its end (launches only, no waits).
 bool bubble_begin(fslbm_ctx *c);
-bool bubble_end(fslbm_ctx *c, hipStream_t st);
+bool bubble_end(fslbm_ctx *c, hipStream_t st, int parity);
 // Every gas and interface cell at p_volume (after a state is loaded).
 bool bubble_reset(fslbm_ctx *c);
 

@@ -28,12 +28,16 @@ def _check(sim, st, what):
     assert err <= 1e-12, f"{what}: bubble pressure error {err:.2e}"
 
 
-def test_enclosed_bubble_step_by_step_then_in_calls():
+@pytest.mark.parametrize("graphs", [True, False], ids=["graph-replay", "direct-launches"])
+def test_enclosed_bubble_step_by_step_then_in_calls(graphs):
+    """Every step after a call's first replays the step and the bubble
+    kernels as one graph; with graphs off they are launched one by one."""
     s = setups.rising_bubbles()
     p = oracle_params(s, bubble_model=1)
     st = oracle_state(s, p)
-    announce("enclosed bubble 24x8x40, bubble model")
+    announce(f"enclosed bubble 24x8x40, bubble model, graphs {'on' if graphs else 'off'}")
     sim = sim_from_states(p, [st])
+    sim.use_graphs(graphs)
     for k in range(1, 6):
         sim.step(1)
         oracle.step(p, st, 1)
