@@ -143,9 +143,11 @@ typedef struct fslbm_params {
                              * bubbles that hold its cells (shared by their gas
                              * volume), so p V is kept, merges add, splits share
                              * one pressure.  Every bubble starts at p_volume.
-                             * Steps run without graphs and without the fused
-                             * excess work; fslbm_step_timed and the reverse mode
-                             * reject it.                                          */
+                             * Each step finishes its own excess work (none is
+                             * fused into the next step's bulk kernel); with
+                             * graphs enabled, every step after a call's first
+                             * replays as one graph with the bubble kernels.
+                             * fslbm_step_timed and the reverse mode reject it.  */
     int32_t diag_every;     /* stability check period K (Sec. 4: the solver is
                              * stable while |u| stays below c_s = 1/sqrt(3)):
                              * 0 off; K > 0: fslbm_step runs the diagnostics
@@ -243,7 +245,9 @@ fslbm_status fslbm_step_timed(fslbm_ctx *ctx, int32_t nsteps, double *bulk_ms, d
 fslbm_status fslbm_refill_scheme(fslbm_ctx *ctx, int32_t scheme);
 
 /* Enable (1) or disable (0) replaying the step sequence as a captured HIP
- * graph (default: enabled).  Results are identical either way. */
+ * graph (default: enabled).  The same kernels run either way; results are
+ * bit-identical but where floating-point atomic sums (the bubble model's
+ * per-bubble sums, the excess-mass reservoir) add in another order. */
 fslbm_status fslbm_use_graphs(fslbm_ctx *ctx, int32_t enable);
 
 /* Change the stream used by later calls (hipStream_t). */
