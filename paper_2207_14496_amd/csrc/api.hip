@@ -511,9 +511,20 @@ bool capture(fslbm_ctx *c, int parity, int pending) {
     return hip_ok(c, ie, "hipGraphInstantiate");
 }
 
-// A step with the bubble model whose start labels are the last step's end
-// labels (bubble_begin has swapped them in): the step with its own excess
-// work, then the labels and pressures of its end, as graph v.
+// The bubble model's end of the step before (its labels and pressures), run
+// between a step's bulk kernel, which finishes that step's excess work, and its
+// interface kernel, the first to read the pressures.
+struct BubbleEnd {
+    fslbm_ctx *c;
+    int parity;   // of the step whose bulk kernel precedes
+};
+void bubble_end_hook(void *arg, hipStream_t s) {
+    const BubbleEnd *h = static_cast<const BubbleEnd *>(arg);
+    (void)bubble_end(h->c, s, h->parity);
+}
+
+// A bubble-model step that finishes the step before inside its bulk kernel and
+// then runs that step's bubble kernels, as graph v.
 bool capture_bubble_step(fslbm_ctx *c, int parity, int v) {
     if (!c->cap_stream &&
         !hip_ok(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "hipStreamCreate"))
@@ -522,15 +533,55 @@ bool capture_bubble_step(fslbm_ctx *c, int parity, int v) {
     if (!hip_ok(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal),
                 "hipStreamBeginCapture"))
         return false;
-    launch_step(make_args(c, parity), c->p.storage, c->p.collision, c->p.refill, c->cap_stream, nullptr,
-                nullptr, true);
-    const bool ok = bubble_end(c, c->cap_stream, 1 - parity);
+    const StepArgs prev = make_args(c, 1 - parity);
+    BubbleEnd h{c, parity};
+    const StepHook hook{bubble_end_hook, &h};
+    launch_step(make_args(c, parity), c->p.storage, c->p.collision, c->p.refill, c->cap_stream, nullptr, &prev,
+                false, &hook);
     hipError_t le = hipGetLastError();
     hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
-    if (!ok || !hip_ok(c, le, "kernel launch (capture)") || !hip_ok(c, e, "hipStreamEndCapture")) return false;
+    if (c->status != FSLBM_OK || !hip_ok(c, le, "kernel launch (capture)") ||
+        !hip_ok(c, e, "hipStreamEndCapture"))
+        return false;
     hipError_t ie = hipGraphInstantiate(&c->exec[v], g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     return hip_ok(c, ie, "hipGraphInstantiate");
+}
+
+// One step with the bubble model.  A step left pending has its excess work run
+// inside this step's bulk kernel and its bubble labels and pressures between
+// this step's bulk and interface kernels (graph replay when enabled); its end
+// labels then become this step's start labels.  finish: this step's own excess
+// work and bubble kernels run at its end.
+bool enqueue_bubble_step(fslbm_ctx *c, bool finish) {
+    const int parity = int(c->t & 1);
+    const StepArgs a = make_args(c, parity);
+    if (!c->pending) {
+        // the step's start labels: the last step's end labels, or labelled now
+        if (!bubble_begin(c)) return false;
+        launch_step(a, c->p.storage, c->p.collision, c->p.refill, c->stream, nullptr, nullptr, false);
+    } else if (c->graphs) {
+        const int v = 4 + parity + 2 * (c->L.blab0 < c->L.blab1 ? 0 : 1);
+        if (!c->exec[v] && !capture_bubble_step(c, parity, v)) return false;
+        if (!hip_ok(c, hipGraphLaunch(c->exec[v], c->stream), "hipGraphLaunch")) return false;
+    } else {
+        const StepArgs prev = make_args(c, 1 - parity);
+        BubbleEnd h{c, parity};
+        const StepHook hook{bubble_end_hook, &h};
+        launch_step(a, c->p.storage, c->p.collision, c->p.refill, c->stream, nullptr, &prev, false, &hook);
+    }
+    if (!hip_ok(c, hipGetLastError(), "step kernel launch") || c->status != FSLBM_OK) return false;
+    if (c->pending) {
+        c->bub_ready = true;
+        if (!bubble_begin(c)) return false;   // the last step's end labels become the start labels
+    }
+    if (finish) {
+        launch_excess(a, c->p.storage, c->stream);
+        if (!hip_ok(c, hipGetLastError(), "k_excess") || !bubble_end(c, c->stream, 1 - parity)) return false;
+    }
+    c->pending = !finish;
+    ++c->t;
+    return true;
 }
 
 bool enqueue_step(fslbm_ctx *c, bool finish) {
@@ -786,28 +837,19 @@ fslbm_status fslbm_step(fslbm_ctx *c, int32_t nsteps) {
     if (c->status != FSLBM_OK) return c->status;
     if (nsteps < 0) return fail(c, FSLBM_EINVAL, "nsteps must be >= 0");
     if (c->p.bubble_model) {
-        // the bubbles of the step's start, the step with its own excess work,
-        // then the bubble pressures of its end (one graph once the start labels
-        // are the last step's end labels)
+        // each step's excess work runs inside the next step's bulk kernel, and
+        // its bubble labels and pressures right after it; the last step of the
+        // call, a step that a stability check follows and every step with
+        // surface tension (its curvature kernel reads the pressures before the
+        // bulk kernel) finish their own
+        const int K = c->p.diag_every;
         for (int32_t s = 0; s < nsteps; ++s) {
-            const bool replay = c->graphs && c->bub_ready;
-            if (!bubble_begin(c)) return c->status;
-            const int parity = int(c->t & 1);
-            if (replay) {
-                const int v = 4 + parity + 2 * (c->L.blab0 < c->L.blab1 ? 0 : 1);
-                if (!c->exec[v] && !capture_bubble_step(c, parity, v)) return c->status;
-                if (!hip_ok(c, hipGraphLaunch(c->exec[v], c->stream), "hipGraphLaunch")) return c->status;
-                c->bub_ready = true;
-            } else {
-                launch_step(make_args(c, parity), c->p.storage, c->p.collision, c->p.refill, c->stream,
-                            nullptr, nullptr, true);
-                if (!hip_ok(c, hipGetLastError(), "step kernel launch")) return c->status;
-                if (!bubble_end(c, c->stream, 1 - parity)) return c->status;
+            const bool checked = K > 0 && (c->t + 1) % K == 0;
+            if (!enqueue_bubble_step(c, s + 1 == nsteps || checked || c->p.sigma != 0.0)) return c->status;
+            if (checked) {
+                const fslbm_status st = check_stability(c);
+                if (st != FSLBM_OK) return st;
             }
-            c->pending = false;
-            ++c->t;
-            const fslbm_status st = check_stability(c);
-            if (st != FSLBM_OK) return st;
         }
         return FSLBM_OK;
     }

@@ -1194,7 +1194,8 @@ static void launch_coll(int coll, int parity, F &&f) {
 
 template <int ST>
 static void launch_step_t(const StepArgs &a, int collision, int scheme, hipStream_t s,
-                          const BulkEvents *ev, const StepArgs *pending, bool finish) {
+                          const BulkEvents *ev, const StepArgs *pending, bool finish,
+                          const StepHook *after_bulk) {
     const int lb = list_blocks(a.cap);
     if (pending && a.rhoG) {
         hipLaunchKernelGGL(k_excess<ST>, dim3(lb), dim3(256), 0, s, *pending);
@@ -1211,6 +1212,7 @@ static void launch_step_t(const StepArgs &a, int collision, int scheme, hipStrea
     launch_coll<ST>(coll, a.parity, [&](auto C, auto P) {
         launch_bulk_t<ST, decltype(C)::value, decltype(P)::value>(a, pending, s, ev);
     });
+    if (after_bulk) after_bulk->fn(after_bulk->arg, s);
     launch_coll<ST>(coll, a.parity, [&](auto C, auto P) {
         hipLaunchKernelGGL((k_interface<ST, decltype(C)::value, decltype(P)::value>), dim3(lb), dim3(256), 0,
                            s, a);
@@ -1237,8 +1239,9 @@ static void launch_step_t(const StepArgs &a, int collision, int scheme, hipStrea
 template <>
 void launch_step_storage<FSLBM_UNIT_STORAGE>(const StepArgs &a, int collision, int scheme,
                                              hipStream_t s, const BulkEvents *ev,
-                                             const StepArgs *pending, bool finish) {
-    launch_step_t<FSLBM_UNIT_STORAGE>(a, collision, scheme, s, ev, pending, finish);
+                                             const StepArgs *pending, bool finish,
+                                             const StepHook *after_bulk) {
+    launch_step_t<FSLBM_UNIT_STORAGE>(a, collision, scheme, s, ev, pending, finish, after_bulk);
 }
 template <>
 void launch_excess_storage<FSLBM_UNIT_STORAGE>(const StepArgs &a, hipStream_t s) {
@@ -1248,12 +1251,12 @@ void launch_excess_storage<FSLBM_UNIT_STORAGE>(const StepArgs &a, hipStream_t s)
 
 #if defined(FSLBM_UNIT_DISPATCH)
 void launch_step(const StepArgs &a, int storage, int collision, int scheme, hipStream_t s,
-                 const BulkEvents *ev, const StepArgs *pending, bool finish) {
+                 const BulkEvents *ev, const StepArgs *pending, bool finish, const StepHook *after_bulk) {
     switch (storage) {
-        case ST_F64: launch_step_storage<ST_F64>(a, collision, scheme, s, ev, pending, finish); break;
-        case ST_F32: launch_step_storage<ST_F32>(a, collision, scheme, s, ev, pending, finish); break;
-        case ST_F16: launch_step_storage<ST_F16>(a, collision, scheme, s, ev, pending, finish); break;
-        default: launch_step_storage<ST_BF16>(a, collision, scheme, s, ev, pending, finish); break;
+        case ST_F64: launch_step_storage<ST_F64>(a, collision, scheme, s, ev, pending, finish, after_bulk); break;
+        case ST_F32: launch_step_storage<ST_F32>(a, collision, scheme, s, ev, pending, finish, after_bulk); break;
+        case ST_F16: launch_step_storage<ST_F16>(a, collision, scheme, s, ev, pending, finish, after_bulk); break;
+        default: launch_step_storage<ST_BF16>(a, collision, scheme, s, ev, pending, finish, after_bulk); break;
     }
 }
 void launch_excess(const StepArgs &a, int storage, hipStream_t s) {
