@@ -143,10 +143,10 @@ typedef struct fslbm_params {
                              * bubbles that hold its cells (shared by their gas
                              * volume), so p V is kept, merges add, splits share
                              * one pressure.  Every bubble starts at p_volume.
-                             * Each step finishes its own excess work (none is
-                             * fused into the next step's bulk kernel); with
-                             * graphs enabled, every step after a call's first
-                             * replays as one graph with the bubble kernels.
+                             * A step's bubble kernels run after the next
+                             * step's bulk kernel (which finishes its excess
+                             * work), before that step's interface kernel; the
+                             * call's last step finishes its own.
                              * fslbm_step_timed and the reverse mode reject it.  */
     int32_t diag_every;     /* stability check period K (Sec. 4: the solver is
                              * stable while |u| stays below c_s = 1/sqrt(3)):
