@@ -127,16 +127,13 @@ __device__ __forceinline__ void uf_join(int32_t *lab, int32_t x, int32_t y) {
     }
 }
 
-// Propagation pass: the smallest label among the cell's and its gas or
-// interface neighbours', then the label of the cell that label names.  Labels
-// only fall and only name cells of the same set.
-__global__ __launch_bounds__(BS) void k_bub_prop(StepArgs a, int32_t *lab) {
-    const long long gid = (long long)blockIdx.x * BS + threadIdx.x;
-    if (gid >= a.g.BN) return;
+// Propagation: the smallest label among the cell's and its gas or interface
+// neighbours', then the label of the cell that label names.  Labels only fall
+// and only name cells of the same set, so a neighbour's label read before or
+// after its own update is valid either way.
+__device__ __forceinline__ void bub_prop_cell(const StepArgs &a, int32_t *lab, const long long gid,
+                                              const Cell &c, const long long cb) {
     const int32_t l0 = lab[gid];
-    if (l0 < 0) return;
-    const Cell c = decode(a.g, gid);
-    const long long cb = (long long)c.b * a.g.N;
     int32_t m = l0;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
@@ -149,13 +146,21 @@ __global__ __launch_bounds__(BS) void k_bub_prop(StepArgs a, int32_t *lab) {
     if (m < l0) lab[gid] = m;
 }
 
-// Every link between two gas or interface cells, once (from the cell whose
-// direction index is the lower of the pair).
-__global__ __launch_bounds__(BS) void k_bub_merge(StepArgs a, int32_t *lab) {
+// After the seed, for every gas or interface cell: NPROP propagation rounds
+// (each pass one launch: a merge must not run beside a propagation round,
+// whose plain store could undo the merge's link), or with MERGE the merge of
+// the two trees of every link (from the cell whose direction index is the
+// lower of the pair).  Two propagation rounds in one launch time the same as
+// two launches; three cost 1.7%.
+template <int NPROP, bool MERGE>
+__global__ __launch_bounds__(BS) void k_bub_link(StepArgs a, int32_t *lab) {
     const long long gid = (long long)blockIdx.x * BS + threadIdx.x;
     if (gid >= a.g.BN || lab[gid] < 0) return;
     const Cell c = decode(a.g, gid);
     const long long cb = (long long)c.b * a.g.N;
+#pragma unroll
+    for (int r = 0; r < NPROP; ++r) bub_prop_cell(a, lab, gid, c, cb);
+    if (!MERGE) return;
     int32_t lq[Q];
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
@@ -226,9 +231,9 @@ unsigned blocks(const StepArgs &a) { return unsigned((a.g.BN + BS - 1) / BS); }
 bool label(fslbm_ctx *c, hipStream_t st, const StepArgs &a, int32_t *lab, const int32_t *lab0, double *V,
            double *kept, double *amount, int32_t *atm) {
     hipLaunchKernelGGL(k_bub_seed, dim3(blocks(a)), dim3(BS), 0, st, a, lab, lab0, V, kept, amount, atm);
-    hipLaunchKernelGGL(k_bub_prop, dim3(blocks(a)), dim3(BS), 0, st, a, lab);
-    hipLaunchKernelGGL(k_bub_prop, dim3(blocks(a)), dim3(BS), 0, st, a, lab);
-    hipLaunchKernelGGL(k_bub_merge, dim3(blocks(a)), dim3(BS), 0, st, a, lab);
+    hipLaunchKernelGGL((k_bub_link<1, false>), dim3(blocks(a)), dim3(BS), 0, st, a, lab);
+    hipLaunchKernelGGL((k_bub_link<1, false>), dim3(blocks(a)), dim3(BS), 0, st, a, lab);
+    hipLaunchKernelGGL((k_bub_link<0, true>), dim3(blocks(a)), dim3(BS), 0, st, a, lab);
     return hip_ok(c, hipGetLastError(), "bubble labels");
 }
 
