@@ -514,8 +514,8 @@ def adjoint_report(fslbm, setups, torch, T=4000, B=64, x_probe=32):
 def bubble_report(fslbm, setups, torch, steps=200, warmup=10):
     """The bubble model (Sec. 2.2, volume pressure of enclosed gas): eight
     bubbles of radius 10 rising in a 128 x 64 x 192 liquid box (periodic x, y),
-    FP32 storage.  Step time with the model and without it (the labels, the
-    per-bubble sums and the direct launches are its cost), the bubble pressure
+    FP32 storage.  Step time with the model and without it (the labels and the
+    per-bubble sums are its cost), the bubble pressure
     range at the end, and the total gas amount sum_k p_k V_k at the start and
     the end (every bubble is enclosed, so the amount is conserved but for the
     gas of cells that fill)."""

@@ -291,7 +291,7 @@ struct StepArgs {
     double trt_lambda;
     double les_k;          // Smagorinsky: 2 C_S^2 / c_s^4 (0 = no turbulence model)
     double sigma, p_volume, eps_phi;
-    SList list_if;          // interface cells of this step, built by the bulk kernel in tile order
+    SList list_if;          // interface cells of this step, built by the bulk kernel by tile groups
     SList list_if_prev;     // the same list of the last step
     SList list_mark;        // interface cells marked for filling or emptying this step
     SList list_band;        // surface band (sigma != 0)

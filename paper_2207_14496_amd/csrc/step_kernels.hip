@@ -4,8 +4,8 @@
 // odd ones, see fslbm_device.hpp), five kernels plus three for surface tension:
 //   [sigma != 0]  k_band -> k_normals -> k_curvature    (Sec. 2.2, curvature)
 //   k_stream_collide  fluid tiles: liquid cells get the in-place stream +
-//                     bounce-back + collide; interface cells are listed in
-//                     tile order
+//                     bounce-back + collide; interface cells are listed by
+//                     groups of neighbouring tiles
 //   k_interface       interface list: the same update plus the mass exchange
 //                     (Sec. 2.2 mass flux with the forced filling/emptying
 //                     table), the anti-bounce-back condition, phi = m/rho and
@@ -24,11 +24,12 @@
 // live in device memory, so the whole sequence can be captured once and
 // replayed as a HIP graph.
 //
-// On MI355X every kernel boundary costs several microseconds (dispatch plus
-// the cross-XCD cache write-back and invalidate), which dominates these short
-// list kernels, so work that can share a kernel does.  Inside the list
-// kernels every load that does not depend on another is issued first, with
-// clamped in-bounds addresses for walls, and only then selected.
+// On MI355X a kernel boundary inside the graph leaves a gap of about a
+// microsecond, and each kernel starts with cold per-XCD caches; the short list
+// kernels are bound by their chains of dependent memory round trips, so work
+// that can share a kernel does, and inside the list kernels every load that
+// does not depend on another is issued first, with clamped in-bounds
+// addresses for walls, and only then selected.
 #include <hip/hip_ext.h>
 
 #include <type_traits>
