@@ -564,7 +564,7 @@ __device__ __forceinline__ bool tile_is_plain(const StepArgs &a, uint32_t gid0, 
 // over that list, so a mostly empty domain does not pay for its gas, and a
 // wavefront never loads a row segment without fluid.  Liquid cells get the full
 // stream-collide update (plain tiles through update_liquid_plain).  Interface
-// cells are listed for k_interface in groups from four neighbouring tiles, so
+// cells are listed for k_interface in groups from eight neighbouring tiles, so
 // the list kernels of the step read neighbouring cells from neighbouring lanes.
 // Cell types are read through type_after: with the last step's excess-mass
 // work running in the same grid, a new interface cell may still carry its
@@ -599,14 +599,14 @@ __device__ __forceinline__ void bulk_part(const StepArgs &a, const int wg, const
             ty = type_after(fl);
             if (ty == F_LIQ) update_cell<ST, COLL, PAR, false>(a, gid, fl);
         }
-        // the interface cells of four consecutive list tiles share a slot, and
+        // the interface cells of eight consecutive list tiles share a slot, and
         // the slots of such groups are scattered by a multiplicative hash:
         // k_interface's wavefronts then take cells of a few neighbouring rows,
         // while the wavefronts that run at the same time work far apart (with
         // the list in tile order and the wavefront's slot, k_interface on the
         // 512x512x96 cylinder in FP64 took 60 us instead of 45)
         slist_append(a.list_if, ty == F_IF, int32_t(gid), a.cnt + C_ERR,
-                     int((uint32_t(k >> 2) * 2654435761u) >> 8));
+                     int((uint32_t(k >> 3) * 2654435761u) >> 8));
     }
 }
 
