@@ -18,6 +18,11 @@ roofline   the bulk stream-collide kernel: algorithmic bytes per launch (per
            the same counters' reading for a device copy of known size
            (--calibrate-copy), when such a measurement of the current kernel
            source is on record.
+event_timed_windows  the same steps in four equal windows of the second
+           context (launched one by one with the bulk kernel's events): per
+           window its steps, fluid and interface cells, step time, MLUPS_fluid and
+           bulk-kernel time, so that the run's phases (the column's collapse)
+           show.
 cpu_baseline  the FP64 CPU oracle (single thread) on a bounded sample of the
            same workload.
 standing_wave_cpu  the 64 x 128 standing wave (SRT omega = 1.8, g = 1e-5, EQ,
@@ -96,11 +101,13 @@ def measured_traffic(workload, storage_name):
     return None
 
 
-def run_case(fslbm, setup, storage, steps, warmup, use_graphs=True):
+def run_case(fslbm, setup, storage, steps, warmup, use_graphs=True, windows=1):
     """`steps` timed steps after `warmup` (graph replay), then the bulk
     kernel's own duration over the same part of the run: a second context from
     the same setup goes through the same warm-up and the same steps with every
-    bulk launch stamped by HIP events of its own dispatch."""
+    bulk launch stamped by HIP events of its own dispatch, in `windows` equal
+    calls, each reported on its own (its steps, fluid cells, step and bulk-kernel
+    time; these steps are launched one by one with their events, not replayed)."""
     import torch
     sim = fslbm.from_setup(setup, storage=storage)
     sim.use_graphs(use_graphs)
@@ -121,10 +128,22 @@ def run_case(fslbm, setup, storage, steps, warmup, use_graphs=True):
     twin = fslbm.from_setup(setup, storage=storage)
     twin.use_graphs(use_graphs)
     twin.step(warmup)
-    bulk_ms, _ = twin.step_timed(steps)
+    bulk_ms, win, t = 0.0, [], warmup
+    for w in range(windows):
+        k = steps // windows + (steps % windows if w == windows - 1 else 0)
+        da = twin.diagnostics()[0]
+        b, tot = twin.step_timed(k)
+        db = twin.diagnostics()[0]
+        bulk_ms += b
+        fl = 0.5 * ((da["n_liquid"] + da["n_interface"]) + (db["n_liquid"] + db["n_interface"]))
+        win.append({"steps": [t, t + k], "fluid_cells_avg": int(fl),
+                    "interface_cells_avg": int(0.5 * (da["n_interface"] + db["n_interface"])),
+                    "ms_per_step": round(tot / k, 5), "mlups_fluid": round(fl * k / (tot * 1e-3) / 1e6, 1),
+                    "bulk_kernel_ms": round(b / k, 5)})
+        t += k
     twin.close()
     out = dict(sim=sim, ms=ms, fluid=fluid, n_if=n_if, n_liq=n_liq, d0=d0, d1=d1,
-               bulk_ms_avg=bulk_ms / steps)
+               bulk_ms_avg=bulk_ms / steps, windows=win)
     return out
 
 
@@ -252,7 +271,7 @@ def main():
     setup = setups.config(args.workload)
     log(f"{setup.nx}x{setup.ny}x{setup.nz}: {setup.fluid_cells()} fluid cells; warmup "
         f"{args.warmup}, timed {args.steps} steps, storage {args.storage}")
-    r = run_case(fslbm, setup, storage, args.steps, args.warmup)
+    r = run_case(fslbm, setup, storage, args.steps, args.warmup, windows=4 if args.steps >= 4 else 1)
     ms_step = r["ms"] / args.steps
     value = r["fluid"] * args.steps / (r["ms"] * 1e-3) / 1e6
     mlups_domain = setup.N * args.steps / (r["ms"] * 1e-3) / 1e6
@@ -279,6 +298,7 @@ def main():
                    "mlups_domain": round(mlups_domain, 1), "mass_drift_rel": mass_drift,
                    "graphs": True, "parallelism": "single GPU"},
         "roofline": rl,
+        "event_timed_windows": r["windows"],
     }
 
     if not args.no_variants:
